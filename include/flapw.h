@@ -1,0 +1,174 @@
+/*
+ * flapw.h -- C-ABI of the MI355X (gfx950) library that generates the muffin-tin parts of the
+ * FLAPW Hamiltonian H and overlap S (Di Napoli, Peise, Hrywniak, Bientinesi, "High-performance
+ * generation of the Hamiltonian and Overlap matrices in FLAPW methods").
+ *
+ * What is computed (the paper's notation):
+ *   A_{L,a,t}, B_{L,a,t}   matching coefficients, appendix A.1, eqs. def_a_tensor / def_b_tensor
+ *   T_a                    [[T^AA, T^AB], [T^BA, T^BB]], appendix A.2, eq. t_matrices
+ *   S = sum_a A_a^H A_a + B_a^H U_a^H U_a B_a       section 2.3 eq. def_overlap, section 4 eqn:S
+ *   H = sum_a [A_a;B_a]^H T_a [A_a;B_a]              section 2.3 eq. def_hamilton, section 4 eqn:H
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - atomic units (bohr, bohr^-1); complex Y_lm orthonormal with the Condon-Shortley phase;
+ *     L = l*l + l + m;
+ *   - A and B rows: atoms stacked in order, each with (lmax(type)+1)^2 rows ordered by L
+ *     (section 4.2 "A_*" layout, section 4.7 ragged blocks);
+ *   - T diagonal: E_l on AA, E_l ||udot_l||^2 on BB, 1/2 on AB and on BA (the Hermitian part of
+ *     the printed +1 / +0, so that T^BA = (T^AB)^H as section 4.4 uses);
+ *   - non-spherical integrals I^{(x,y)} are indexed [type][l'][l][L''], bra function first
+ *     (eq. nonsph_integrals), L'' = l''^2 + l'' + m'';
+ *   - K_t = 0 uses the z direction for Khat (only l = 0 survives there);
+ *   - H and S are written on the upper triangle including the diagonal only (column-major
+ *     'U'; the strictly lower part is left untouched); the diagonal's imaginary parts are
+ *     set to exactly zero.  (The paper's BLAS calls write the lower triangle; both hold the
+ *     same Hermitian matrix.)
+ *
+ * Memory and ownership: arrays marked [device] live in GPU memory of the current HIP device,
+ * arrays marked [host] in host memory.  The caller allocates and owns every input and output
+ * buffer; the library keeps no pointer to them after a call returns.  Work buffers belong to
+ * the handle and are reused across calls; a handle must not be used by two threads at once.
+ * Every computing call is asynchronous with respect to the host and ordered on `stream`
+ * (a hipStream_t; NULL is the default stream).  All dense matrices are column-major
+ * complex128 ({re, im} pairs) with an explicit leading dimension (section 4.1 storage format).
+ *
+ * Errors: arguments are validated before any launch; on FLAPW_ERR_ARG, FLAPW_ERR_WRONSKIAN or
+ * FLAPW_ERR_NOT_HERMITIAN no output is touched.  FLAPW_ERR_DEVICE leaves outputs undefined.
+ * flapw_last_error() returns a human-readable message for the last failure on a handle.
+ * No C++ exception crosses this interface.
+ */
+#ifndef FLAPW_H
+#define FLAPW_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } flapw_z;     /* complex128 */
+typedef struct flapw_context *flapw_handle;
+typedef void *flapw_stream;                    /* hipStream_t */
+
+typedef enum {
+    FLAPW_OK = 0,
+    FLAPW_ERR_ARG = -1,            /* invalid argument (null pointer, size, leading dimension, ...) */
+    FLAPW_ERR_WRONSKIAN = -2,      /* |W_{l,type}| too small: coefficients undefined */
+    FLAPW_ERR_NOT_HERMITIAN = -3,  /* non-spherical integrals would make T non-Hermitian */
+    FLAPW_ERR_NOMEM = -4,          /* device work buffer allocation failed */
+    FLAPW_ERR_DEVICE = -5,         /* a HIP call failed */
+    FLAPW_ERR_UNSUPPORTED = -6     /* request outside what the library implements */
+} flapw_status;
+
+/* Arithmetic of the S and H contractions.  Coefficients, T and the per-atom panels T_a P_a
+ * are always FP64.
+ *   FP64        FP64 matrix cores throughout (complex128 accumulation).
+ *   SPLIT_BF16  each FP64 operand column is split, with one power-of-two scale per column,
+ *               into `slices` signed 8-bit digits held in bfloat16; digit products run on
+ *               BF16 matrix cores and accumulate exactly in FP32 over chunks of at most 256
+ *               products; chunks are recombined and summed over atoms in FP64.
+ *   SPLIT_I8    the same with 7-bit digits in int8 and exact int32 accumulation. */
+typedef enum {
+    FLAPW_PREC_FP64 = 0,
+    FLAPW_PREC_SPLIT_BF16 = 1,
+    FLAPW_PREC_SPLIT_I8 = 2
+} flapw_prec;
+
+#define FLAPW_LMAX_CAP 12          /* largest supported l_max per type */
+#define FLAPW_LPOT_CAP 12          /* largest supported l'' of the non-spherical potential */
+#define FLAPW_SLICES_CAP 8         /* largest number of digits per operand in split precision */
+
+/* Per atom type tau = 0..n_types-1 and l = 0..lmax[tau]; per-l arrays have row stride
+ * `lstride` (>= max lmax + 1) and are indexed [tau * lstride + l].  [host] */
+typedef struct {
+    int n_types;
+    int lstride;
+    const int *lmax;          /* [n_types] l_max of the type, 0..FLAPW_LMAX_CAP */
+    const double *rmt;        /* [n_types] muffin-tin radius R (bohr), > 0 */
+    const double *u;          /* u_l(R) */
+    const double *du;         /* u_l'(R)   (radial derivative) */
+    const double *ud;         /* udot_l(R) (energy derivative) */
+    const double *dud;        /* udot_l'(R) */
+    const double *ud_norm2;   /* ||udot_l||^2 over the sphere (eq. def_overlap) */
+    const double *e_l;        /* energy parameter E_l (eq. t_matrices) */
+} flapw_radial;
+
+/* Atoms.  [host] */
+typedef struct {
+    int n_atoms;
+    const int *type;          /* [n_atoms] type index */
+    const double *pos;        /* [n_atoms][3] Cartesian position x_a (bohr) */
+    const double *rot;        /* [n_atoms][3][3] row-major orthogonal R_a; Y_lm is taken at R_a Khat */
+    double omega;             /* unit-cell volume (bohr^3), > 0 */
+} flapw_atoms;
+
+/* Non-spherical radial integrals (eq. nonsph_integrals), each [n_types][lstride][lstride][(lpot+1)^2]
+ * indexed [tau][l'][l][L''] (bra l' first).  Hermitian T requires I^{uu} and I^{udot udot}
+ * symmetric in (l', l), I^{udot u}_{l',l,L''} = I^{u udot}_{l,l',L''}, and the reality rule
+ * I_{(l'',-m)} = (-1)^m I_{(l'',m)}; flapw_build_T checks this.  [host] */
+typedef struct {
+    int lpot;                 /* l''_max, 0..FLAPW_LPOT_CAP */
+    const double *i_uu;       /* I^{(u,u)} */
+    const double *i_ud;       /* I^{(u,udot)} */
+    const double *i_du;       /* I^{(udot,u)} */
+    const double *i_dd;       /* I^{(udot,udot)} */
+} flapw_potential;
+
+/* Handle life cycle.  flapw_create binds the handle to the current HIP device. */
+flapw_status flapw_create(flapw_handle *h);
+flapw_status flapw_destroy(flapw_handle h);
+const char *flapw_status_string(flapw_status s);
+const char *flapw_last_error(flapw_handle h);
+/* Device memory held by the handle's work buffers, in bytes. */
+long long flapw_workspace_bytes(flapw_handle h);
+
+/* Matching coefficients A_* and B_* of one k-point (appendix A.1, eqs. def_a_tensor,
+ * def_b_tensor; Wronskian W = udot u' - u udot'; stacked layout of section 4.2).
+ *   k      [host]   k-point, Cartesian (bohr^-1)
+ *   g      [device] n_g x 3 doubles, Cartesian G_t (row t = basis function t); K_t = k + G_t
+ *   A, B   [device] K x n_g, column-major, leading dimension ld >= K = sum_a (lmax(type_a)+1)^2
+ * Errors: FLAPW_ERR_ARG (n_g < 1, ld < K, bad type/l_max, omega <= 0, R_a not orthogonal to
+ * 1e-10), FLAPW_ERR_WRONSKIAN (|W| <= 1e-12 max(|udot u'|, |u udot'|) for some used (type, l)). */
+flapw_status flapw_coeffs(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
+                          const flapw_radial *rad, flapw_z *A, flapw_z *B, long ld, flapw_stream stream);
+
+/* T matrices of all atom types (appendix A.2, eqs. gaunt, t_matrices); the Gaunt coefficients
+ * are evaluated on the device.
+ *   T [device] n_types matrices of ldt x ldt complex128, type tau at T + tau * ldt * ldt, each
+ *             holding its 2NL x 2NL matrix (NL = (lmax+1)^2) in the top-left corner, column-major,
+ *             rows = bra (L'), columns = ket (L), blocks [[AA, AB], [BA, BB]].  ldt >= 2 NL_max.
+ *             Entries outside the 2NL x 2NL corner are set to zero.
+ * Errors: FLAPW_ERR_ARG, FLAPW_ERR_NOT_HERMITIAN (integral symmetries violated by more than
+ * 1e-12 of the largest |I|). */
+flapw_status flapw_build_T(flapw_handle h, const flapw_radial *rad, const flapw_potential *pot, flapw_z *T,
+                           long ldt, flapw_stream stream);
+
+/* S and H from given coefficients and T (the contraction stage on its own):
+ *   S = sum_a A_a^H A_a + B_a^H diag(||udot||^2) B_a,   H = sum_a P_a^H T_type(a) P_a,  P_a = [A_a; B_a].
+ *   A, B [device] K x n_g (lda >= K), stacked as flapw_coeffs writes them
+ *   T    [device] as flapw_build_T writes it (must be Hermitian; it is not re-checked)
+ *   H, S [device] n_g x n_g, ldh >= n_g; upper triangle written
+ * `at` supplies n_atoms and type (positions and rotations are not read); `rad` supplies
+ * n_types, lmax and ud_norm2.  slices: digits per operand for the split precisions
+ * (1..FLAPW_SLICES_CAP; 0 = library default); ignored for FP64. */
+flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, const flapw_radial *rad,
+                               const flapw_z *A, const flapw_z *B, long lda, const flapw_z *T, long ldt,
+                               flapw_z *H, flapw_z *S, long ldh, flapw_prec prec, int slices,
+                               flapw_stream stream);
+
+/* The whole path for n_k k-points (one H and one S per k-point, section 2.3): coefficients,
+ * T, per-atom panels and the S/H contractions, all k-points of a memory batch in one grouped
+ * launch of the contraction kernel.
+ *   k    [host] n_k x 3 doubles, Cartesian
+ *   n_g  [host] n_k basis sizes (each >= 1)
+ *   g    [host] n_k pointers to [device] n_g[i] x 3 doubles (Cartesian G)
+ *   H, S [host] n_k pointers to [device] n_g[i] x n_g[i] outputs with leading dimensions
+ *        ldh[i] >= n_g[i] ([host] array)
+ * Errors as flapw_coeffs and flapw_build_T. */
+flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const int *n_g, const double *const *g,
+                               const flapw_atoms *at, const flapw_radial *rad, const flapw_potential *pot,
+                               flapw_z *const *H, flapw_z *const *S, const long *ldh, flapw_prec prec, int slices,
+                               flapw_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLAPW_H */

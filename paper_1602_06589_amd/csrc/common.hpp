@@ -1,0 +1,102 @@
+// Internal declarations shared by the library's HIP sources (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "flapw.h"
+
+namespace flapw {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Per atom, as the coefficient kernel reads it.
+struct AtomDev {
+    double pos[3];
+    double rot[9];        // row-major R_a
+    int type;
+    int nl;               // (lmax(type)+1)^2
+    long long rowA;       // first output row of this atom's A block
+    long long rowB;       // first output row of this atom's B block
+};
+
+// Per (type, l) radial boundary data, as the coefficient kernel reads it.
+struct RadialDev {
+    double u, du, ud, dud;
+    double inv_w;         // 1 / W, W = udot u' - u udot'
+};
+
+constexpr int kMaxTypes = 64;
+constexpr int kLStride = FLAPW_LMAX_CAP + 1;
+
+struct TypeDev {
+    double rmt;
+    int lmax;
+    int pad;
+    RadialDev rad[kLStride];
+};
+
+// One k-point problem of the contraction stage (padded work layout).
+//   P, Q : kp2 x np complex, column-major (ld = ldp).  Rows are the atoms in order, each as
+//          [A_a (NL_a rows); B_a (NL_a rows)], followed by zero rows up to kp2.  Columns
+//          n..np-1 are zero.
+//   d    : kp2 row weights of S (1 on A rows, ||udot_l||^2 on B rows, 0 on padding).
+struct ProblemDev {
+    const double2 *P;
+    const double2 *Q;
+    const double *d;
+    double2 *H;
+    double2 *S;
+    long long ldp;
+    long long ldh;
+    int n;
+    int kp2;
+};
+
+// Split-precision operands of one k-point (see split.hip).
+struct SplitProblemDev {
+    const void *L;        // left digits  [slice][plane re/im][np][kp2b]   (bytes per digit: esz)
+    const void *R;        // right digits for S (the d-weighted P)
+    const void *RQ;       // right digits for H (Q)
+    const int *eL;        // per-column exponents of the left operand  [np]
+    const int *eR;
+    const int *eRQ;
+    double2 *H;
+    double2 *S;
+    long long ldh;
+    long long plane;      // elements per (slice, re/im) plane = np * kp2
+    int n;
+    int kp2;              // contraction rows (padded)
+};
+
+struct TileDev {
+    int prob;             // problem index
+    int ti;               // tile row
+    int tj;               // tile column (ti <= tj)
+    int pad;
+};
+
+// kernel launchers (return hipError_t of the launch)
+hipError_t launch_coeffs(const double kvec[3], int n_g, int n_cols, const double *g, const AtomDev *atoms, int n_atoms,
+                         const TypeDev *types, int n_types, double pref, double2 *A, double2 *B, long long ld,
+                         long long zero_rows_from, long long zero_rows_to, hipStream_t s);
+
+hipError_t launch_legendre_table(int lt, int nq, const double *z, double *theta, hipStream_t s);
+hipError_t launch_tmat(int n_types, const int *lmax_dev, int lstride, int lpot, int nq, const double *w,
+                       const double *theta, const double *i_uu, const double *i_ud, const double *i_du,
+                       const double *i_dd, const double *e_l, const double *ud_norm2, double2 *T, long long ldt,
+                       hipStream_t s);
+
+hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, const int *atom_type, const int *atom_nl2,
+                         const long long *atom_row, int n_atoms, const double2 *P, double2 *Q, long long ldp, int np,
+                         hipStream_t s);
+
+hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_tiles, hipStream_t s);
+
+hipError_t launch_repack(const double2 *A, const double2 *B, long long lda, int n_g, const AtomDev *atoms,
+                         int n_atoms, const long long *src_off, double2 *P, long long ldp, int kp2, int np,
+                         hipStream_t s);
+
+constexpr int kTile = 64;     // output tile edge (complex elements) of the contraction kernels
+constexpr int kKTile = 16;    // contraction rows per pipeline stage (FP64 kernels)
+
+}  // namespace flapw

@@ -1,0 +1,107 @@
+// The handle behind flapw_handle, and small host helpers shared by the library's host code.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "flapw.h"
+
+namespace flapw {
+
+// A device buffer that only grows.
+struct DevBuf {
+    void *p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t bytes)
+    {
+        if (bytes <= n && p) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            p = nullptr;
+            n = 0;
+            if (e != hipSuccess) return e;
+        }
+        const size_t want = std::max<size_t>(bytes, 256);
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return e;
+        }
+        n = want;
+        return hipSuccess;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+inline long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
+
+constexpr int kRowAlign = 256;      // contraction rows of the work layout are padded to this
+
+}  // namespace flapw
+
+struct flapw_context {
+    int device = 0;
+    std::string err;
+    flapw::DevBuf work;        // P and Q panels of the k-points of one batch
+    flapw::DevBuf tmat;        // T of all types (ldt x ldt each)
+    flapw::DevBuf tables;      // atoms, types, row weights, Q-kernel tables, repack map
+    flapw::DevBuf gaunt;       // Legendre table, quadrature nodes, integrals
+    flapw::DevBuf tiles;       // problem descriptors and tile list of a contraction launch
+    flapw::DevBuf digits;      // split precision: digit planes and column exponents
+    flapw::DevBuf sdesc;       // split precision: descriptors
+    std::vector<unsigned char> host_tables, host_gaunt, host_tiles, host_sdesc;
+    std::vector<long long> host_src;
+};
+
+namespace flapw {
+
+inline flapw_status fail(flapw_handle h, flapw_status s, const std::string &msg)
+{
+    if (h) h->err = msg;
+    return s;
+}
+
+inline flapw_status dev_fail(flapw_handle h, hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(h, e == hipErrorOutOfMemory ? FLAPW_ERR_NOMEM : FLAPW_ERR_DEVICE, m);
+}
+
+// Append `count` objects to a byte buffer at a 256-byte aligned offset; returns the offset.
+template <class T>
+size_t put(std::vector<unsigned char> &buf, const T *src, size_t count)
+{
+    const size_t off = (size_t)round_up((long long)buf.size(), 256);
+    buf.resize(off + sizeof(T) * count);
+    if (count) std::memcpy(buf.data() + off, src, sizeof(T) * count);
+    return off;
+}
+
+// Host-to-device copy of a descriptor buffer (pageable source; the copy is staged before the
+// call returns, and the source vector lives in the handle until the next call anyway).
+inline flapw_status upload(flapw_handle h, DevBuf &dst, const std::vector<unsigned char> &src, hipStream_t s)
+{
+    hipError_t e = dst.ensure(src.size());
+    if (e != hipSuccess) return dev_fail(h, e, "allocating descriptor buffer");
+    e = hipMemcpyAsync(dst.p, src.data(), src.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return dev_fail(h, e, "uploading descriptors");
+    return FLAPW_OK;
+}
+
+// split precision (split.hip)
+flapw_status split_contraction(flapw_handle h, long long kp2, const std::vector<ProblemDev> &probs,
+                               const std::vector<TileDev> &tiles, flapw_prec prec, int slices, hipStream_t s);
+void split_release(flapw_handle h);
+long long split_bytes(flapw_handle h);
+
+}  // namespace flapw

@@ -1,0 +1,239 @@
+"""Python binding of the C-ABI in include/flapw.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libflapw_hip.so`` built next to this file; torch
+supplies device memory (complex128 tensors) and the current HIP stream.  There is no
+fallback: if the library is missing or the GPU is absent the calls raise.
+
+Array conventions (all dense matrices are column-major, as the library's):
+  A, B   torch complex128 tensors of shape (n_g, ld): row t is column t of the K x n_g matrix
+  T      torch complex128 tensor of shape (n_types, ldt, ldt): T[tau][c][r] is entry (r, c)
+  H, S   torch complex128 tensors of shape (n_g, ldh): H[t][r] is entry (r, t); only r <= t is
+         written.  ``hermitian_full`` expands such a tensor to the full matrix.
+
+A `system` argument is any object with the attributes of a FLAPW problem:
+  lmax (n_types,) int, rmt, u, du, ud, dud, ud_norm2, e_l ((n_types, lstride) float),
+  atom_type (n_atoms,) int, pos (n_atoms, 3), rot (n_atoms, 3, 3), omega,
+  lpot and i_uu, i_ud, i_du, i_dd ((n_types, lstride, lstride, (lpot+1)^2) float).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libflapw_hip.so")
+
+FP64, SPLIT_BF16, SPLIT_I8 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "bf16": SPLIT_BF16, "i8": SPLIT_I8}
+
+_STATUS = {0: "FLAPW_OK", -1: "FLAPW_ERR_ARG", -2: "FLAPW_ERR_WRONSKIAN", -3: "FLAPW_ERR_NOT_HERMITIAN",
+           -4: "FLAPW_ERR_NOMEM", -5: "FLAPW_ERR_DEVICE", -6: "FLAPW_ERR_UNSUPPORTED"}
+
+EXPORTS = ["flapw_create", "flapw_destroy", "flapw_status_string", "flapw_last_error", "flapw_workspace_bytes",
+           "flapw_coeffs", "flapw_build_T", "flapw_hs_contract", "flapw_hs_generate"]
+
+
+class FlapwError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Radial(ctypes.Structure):
+    _fields_ = [("n_types", ctypes.c_int), ("lstride", ctypes.c_int), ("lmax", ctypes.c_void_p),
+                ("rmt", ctypes.c_void_p), ("u", ctypes.c_void_p), ("du", ctypes.c_void_p), ("ud", ctypes.c_void_p),
+                ("dud", ctypes.c_void_p), ("ud_norm2", ctypes.c_void_p), ("e_l", ctypes.c_void_p)]
+
+
+class _Atoms(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int), ("type", ctypes.c_void_p), ("pos", ctypes.c_void_p),
+                ("rot", ctypes.c_void_p), ("omega", ctypes.c_double)]
+
+
+class _Potential(ctypes.Structure):
+    _fields_ = [("lpot", ctypes.c_int), ("i_uu", ctypes.c_void_p), ("i_ud", ctypes.c_void_p),
+                ("i_du", ctypes.c_void_p), ("i_dd", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libflapw_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise FileNotFoundError(f"{path} is missing: build it with paper_1602_06589_amd/build.py")
+        lib = ctypes.CDLL(path)
+        P, I, L = ctypes.c_void_p, ctypes.c_int, ctypes.c_long
+        lib.flapw_create.argtypes = [ctypes.POINTER(P)]
+        lib.flapw_destroy.argtypes = [P]
+        lib.flapw_status_string.argtypes = [I]
+        lib.flapw_status_string.restype = ctypes.c_char_p
+        lib.flapw_last_error.argtypes = [P]
+        lib.flapw_last_error.restype = ctypes.c_char_p
+        lib.flapw_workspace_bytes.argtypes = [P]
+        lib.flapw_workspace_bytes.restype = ctypes.c_longlong
+        lib.flapw_coeffs.argtypes = [P, P, I, P, P, P, P, P, L, P]
+        lib.flapw_build_T.argtypes = [P, P, P, P, L, P]
+        lib.flapw_hs_contract.argtypes = [P, I, P, P, P, P, L, P, L, P, P, L, I, I, P]
+        lib.flapw_hs_generate.argtypes = [P, I, P, P, P, P, P, P, P, P, P, I, I, P]
+        for f in EXPORTS:
+            getattr(lib, f).restype = getattr(lib, f).restype or ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+def _dptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def k_rows(system) -> int:
+    lm = np.asarray(system.lmax)[np.asarray(system.atom_type)]
+    return int(((lm + 1) ** 2).sum())
+
+
+def hermitian_full(M):
+    """Expand an upper-triangle column-major result tensor (n, ld) to the full (n x n) matrix."""
+    import torch
+    n = M.shape[0]
+    U = torch.triu(M[:, :n].transpose(0, 1))
+    return U + torch.triu(U, 1).conj().transpose(0, 1)
+
+
+class Flapw:
+    """One library handle (owns the device work buffers).  Use as a context manager."""
+
+    def __init__(self):
+        self._lib = load_library()
+        self._h = ctypes.c_void_p()
+        self._check(self._lib.flapw_create(ctypes.byref(self._h)))
+        self._keep = []
+
+    def close(self):
+        if self._h:
+            self._lib.flapw_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != 0:
+            msg = self._lib.flapw_last_error(self._h).decode() if self._h else ""
+            raise FlapwError(st, msg)
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self._lib.flapw_workspace_bytes(self._h))
+
+    # --------------------------------------------------------------------- descriptors
+    def _radial(self, s):
+        arrs = [_i32(s.lmax), _f64(s.rmt), _f64(s.u), _f64(s.du), _f64(s.ud), _f64(s.dud), _f64(s.ud_norm2),
+                _f64(s.e_l)]
+        self._keep += arrs
+        return _Radial(len(arrs[0]), int(np.asarray(s.u).shape[1]), *[_ptr(a) for a in arrs])
+
+    def _atoms(self, s):
+        arrs = [_i32(s.atom_type), _f64(s.pos), _f64(s.rot)]
+        self._keep += arrs
+        return _Atoms(len(arrs[0]), _ptr(arrs[0]), _ptr(arrs[1]), _ptr(arrs[2]), float(s.omega))
+
+    def _potential(self, s):
+        arrs = [_f64(s.i_uu), _f64(s.i_ud), _f64(s.i_du), _f64(s.i_dd)]
+        self._keep += arrs
+        return _Potential(int(s.lpot), *[_ptr(a) for a in arrs])
+
+    # --------------------------------------------------------------------- calls
+    def coeffs(self, system, k, g, A=None, B=None, stream=None):
+        """A_*, B_* of one k-point.  g: device tensor (n_g, 3) float64 of Cartesian G."""
+        import torch
+        self._keep = []
+        n_g = int(g.shape[0])
+        kr = k_rows(system)
+        if A is None:
+            A = torch.zeros((n_g, kr), dtype=torch.complex128, device=g.device)
+        if B is None:
+            B = torch.zeros((n_g, kr), dtype=torch.complex128, device=g.device)
+        kk = _f64(k)
+        rad, at = self._radial(system), self._atoms(system)
+        self._check(self._lib.flapw_coeffs(self._h, _ptr(kk), n_g, _dptr(g), ctypes.byref(at), ctypes.byref(rad),
+                                           _dptr(A), _dptr(B), int(A.shape[1]), _stream(stream)))
+        return A, B
+
+    def build_T(self, system, ldt: Optional[int] = None, device="cuda", stream=None):
+        import torch
+        self._keep = []
+        nlmax = int((np.max(system.lmax) + 1) ** 2)
+        ldt = ldt or 2 * nlmax
+        T = torch.empty((len(system.lmax), ldt, ldt), dtype=torch.complex128, device=device)
+        rad, pot = self._radial(system), self._potential(system)
+        self._check(self._lib.flapw_build_T(self._h, ctypes.byref(rad), ctypes.byref(pot), _dptr(T), ldt,
+                                            _stream(stream)))
+        return T
+
+    def hs_contract(self, system, A, B, T, prec="fp64", slices: int = 0, H=None, S=None, stream=None):
+        import torch
+        self._keep = []
+        n_g = int(A.shape[0])
+        if H is None:
+            H = torch.zeros((n_g, n_g), dtype=torch.complex128, device=A.device)
+        if S is None:
+            S = torch.zeros((n_g, n_g), dtype=torch.complex128, device=A.device)
+        rad, at = self._radial(system), self._atoms(system)
+        self._check(self._lib.flapw_hs_contract(self._h, n_g, ctypes.byref(at), ctypes.byref(rad), _dptr(A), _dptr(B),
+                                                int(A.shape[1]), _dptr(T), int(T.shape[-1]), _dptr(H), _dptr(S),
+                                                int(H.shape[1]), PRECISIONS.get(prec, prec), int(slices),
+                                                _stream(stream)))
+        return H, S
+
+    def hs_generate(self, system, kpts, gvecs: Sequence, prec="fp64", slices: int = 0, out: Optional[List] = None,
+                    stream=None):
+        """H and S of every k-point.  gvecs: device tensors (n_g_i, 3).  Returns [(H_i, S_i)]."""
+        import torch
+        self._keep = []
+        nk = len(gvecs)
+        ng = np.array([int(g.shape[0]) for g in gvecs], dtype=np.int32)
+        if out is None:
+            out = [(torch.zeros((int(n), int(n)), dtype=torch.complex128, device=gvecs[0].device),
+                    torch.zeros((int(n), int(n)), dtype=torch.complex128, device=gvecs[0].device)) for n in ng]
+        kk = _f64(np.asarray(kpts).reshape(nk, 3))
+        gp = (ctypes.c_void_p * nk)(*[_dptr(g) for g in gvecs])
+        hp = (ctypes.c_void_p * nk)(*[_dptr(h) for h, _ in out])
+        sp = (ctypes.c_void_p * nk)(*[_dptr(s) for _, s in out])
+        ld = np.array([int(h.shape[1]) for h, _ in out], dtype=np.int64)
+        rad, at, pot = self._radial(system), self._atoms(system), self._potential(system)
+        self._check(self._lib.flapw_hs_generate(self._h, nk, _ptr(kk), _ptr(ng), gp, ctypes.byref(at),
+                                                ctypes.byref(rad), ctypes.byref(pot), hp, sp, _ptr(ld),
+                                                PRECISIONS.get(prec, prec), int(slices), _stream(stream)))
+        return out

@@ -1,0 +1,135 @@
+"""Host-side checks of the C-ABI library (no GPU needed): the library loads, exports every
+symbol the header declares, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import synthcells
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "flapw.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1602_06589_amd import build, flapw
+    if not os.path.exists(flapw.LIB_PATH):
+        build.build()
+    return flapw.load_library()
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(flapw_[a-z_A-Z0-9]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported(lib):
+    from paper_1602_06589_amd import flapw
+    declared = _declared()
+    assert set(declared) == set(flapw.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", flapw.LIB_PATH], capture_output=True, text=True).stdout
+    syms = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    for name in declared:
+        assert name in syms, name
+        assert hasattr(lib, name)
+
+
+def test_status_strings(lib):
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.flapw_status_string(s)
+    assert lib.flapw_status_string(-2) == b"vanishing Wronskian"
+
+
+@pytest.fixture()
+def handle(lib):
+    from paper_1602_06589_amd.flapw import Flapw
+    f = Flapw()
+    yield f
+    f.close()
+
+
+class _FakeTensor:
+    """Stands in for a device tensor in calls that must fail before any device access."""
+
+    def __init__(self, shape, ptr=0x1000):
+        self.shape = shape
+        self._p = ptr
+        self.device = "cpu"
+
+    def data_ptr(self):
+        return self._p
+
+
+def _call_coeffs(f, cell, ld=None, n_g=None):
+    from paper_1602_06589_amd import flapw as F
+    f._keep = []
+    rad, at = f._radial(cell), f._atoms(cell)
+    k = np.zeros(3)
+    n = cell.n_g(0) if n_g is None else n_g
+    return f._lib.flapw_coeffs(f._h, F._ptr(k), n, ctypes.c_void_p(0x1000), ctypes.byref(at), ctypes.byref(rad),
+                               ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000),
+                               cell.k_rows() if ld is None else ld, ctypes.c_void_p(0))
+
+
+def test_validation_ld_and_sizes(handle):
+    cell = synthcells.config(0)
+    assert _call_coeffs(handle, cell, ld=cell.k_rows() - 1) == -1
+    assert b"ld" in handle._lib.flapw_last_error(handle._h)
+    assert _call_coeffs(handle, cell, n_g=0) == -1
+
+
+def test_validation_wronskian(handle):
+    cell = synthcells.config(0)
+    cell.u[0, 3] = cell.ud[0, 3] * cell.du[0, 3] / cell.dud[0, 3]      # W = 0 exactly
+    assert _call_coeffs(handle, cell) == -2
+
+
+def test_validation_rotation(handle):
+    cell = synthcells.config(0)
+    cell.rot[1, 0, 0] = 1.01
+    assert _call_coeffs(handle, cell) == -1
+
+
+def test_validation_lmax_cap(handle):
+    cell = synthcells.config(0)
+    cell.lmax[0] = 13
+    assert _call_coeffs(handle, cell) == -1
+
+
+def test_no_device_after_validation(handle):
+    """On a machine without a GPU a valid call reaches the device check and reports it."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    cell = synthcells.config(0)
+    assert _call_coeffs(handle, cell) == -5
+
+
+def _call_build_T(f, cell):
+    f._keep = []
+    rad, pot = f._radial(cell), f._potential(cell)
+    ldt = 2 * int((cell.lmax.max() + 1) ** 2)
+    return f._lib.flapw_build_T(f._h, ctypes.byref(rad), ctypes.byref(pot), ctypes.c_void_p(0x1000), ldt,
+                                ctypes.c_void_p(0))
+
+
+def test_validation_not_hermitian(handle):
+    cell = synthcells.config(0)
+    cell.i_uu[0, 2, 3, 5] += 1e-3                                      # breaks (l', l) symmetry
+    assert _call_build_T(handle, cell) == -3
+    cell = synthcells.config(0)
+    cell.i_ud[0, 2, 3, 5] += 1e-3                                      # breaks I^{udot u} = I^{u udot}^T
+    assert _call_build_T(handle, cell) == -3
+    cell = synthcells.config(0)
+    cell.i_dd[0, 2, 2, 5] += 1e-3                                      # breaks the reality rule in m''
+    assert _call_build_T(handle, cell) == -3
+
+
+def test_validation_lpot(handle):
+    cell = synthcells.config(0)
+    cell.lpot = 13
+    assert _call_build_T(handle, cell) == -1
