@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark: H and S generation (coefficients -> T -> per-atom panels -> S/H contractions) on
+one MI355X, for the seeded synthetic workloads of synthcells.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--precs i8,fp64] [--slices s]
+
+A step is one flapw_hs_generate call over every k-point of the workload (the whole path).
+Inputs (G lists) are resident in HBM before timing starts; K timed steps are bracketed by
+torch.cuda.synchronize().  Prints one JSON line:
+  value      algorithmic TFLOP/s of the headline path (the first of --precs), F_alg per k-point
+             = 16 K N(N+1) + 32 N sum_a NL_a^2 (S and H upper triangles + panels T_a P_a)
+  roofline   the dominant kernel (the S/H contraction), its average launch time from HIP events
+             recorded by the library on the launch stream
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload; the sampled
+             entries also give the relative Frobenius error of every measured path
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {"fp64": 78.6, "bf16": 2500.0, "i8": 5000.0}        # MI355X dense matrix-core peaks, T(FL)OP/s
+KERNEL = {"fp64": "hs_fp64", "bf16": "hs_split", "i8": "hs_split"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
+
+
+def kernel_sources_sha(prec: str) -> str:
+    names = ["contract_fp64.hip", "common.hpp"] if prec == "fp64" else ["split.hip", "common.hpp"]
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1602_06589_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(prec: str, workload: str):
+    """HBM bytes per launch of the contraction kernel from the committed rocprofv3 counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    sha = kernel_sources_sha(prec)
+    for line in open(TRAFFIC_FILE):
+        if not line.startswith("traffic "):
+            continue
+        kv = dict(x.split("=", 1) for x in line.split()[1:])
+        if kv.get("kernel") == KERNEL[prec] and kv.get("workload") == workload and kv.get("src_sha") == sha:
+            return float(kv["bytes_per_launch"])
+    return None
+
+
+def cpu_baseline_leg(cell, outs, nsamp: int):
+    """The oracle on a bounded sample (k-point 0: an nsamp x nsamp block of basis functions,
+    H and S), timed on the host cores.  Also returns the relative Frobenius error of each GPU
+    path on those entries (upper triangle)."""
+    import oracle
+    oracle._load()
+    ik = 0
+    n = cell.n_g(ik)
+    rng = np.random.default_rng(4242)
+    idx = np.sort(rng.choice(n, min(nsamp, n), replace=False))
+    t0 = time.perf_counter()
+    T = oracle.tmat_all(cell)
+    Ho, So = oracle.hs_sampled(cell, ik, idx, idx, T)
+    dt = time.perf_counter() - t0
+    k = cell.k_rows()
+    nl = cell.nl_atom().astype(float)
+    flops = 2 * len(idx) * len(idx) * 16.0 * k + 2 * len(idx) * 32.0 * float((nl * nl).sum())
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    up = idx[:, None] <= idx[None, :]
+    errs = {}
+    for prec, (H, S) in outs.items():
+        Hn = H[0].cpu().numpy() if isinstance(H, list) else H.cpu().numpy()
+        Sn = S[0].cpu().numpy() if isinstance(S, list) else S.cpu().numpy()
+        e = {}
+        for name, M, R in (("H", Hn, Ho), ("S", Sn, So)):
+            got = M[np.ix_(idx, idx)].T
+            e[name] = float(np.linalg.norm((got - R)[up]) / np.linalg.norm(R[up]))
+        errs[prec] = e
+    base = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"k-point 0 of {cell.name}: H and S on a {len(idx)}x{len(idx)} block of basis functions "
+                      f"(coefficients of those columns, T, per-atom panels), {dt:.1f} s",
+            "seconds": dt}
+    return base, errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--precs", default="fp64")
+    ap.add_argument("--slices", type=int, default=0)
+    ap.add_argument("--nk", type=int, default=0, help="use only the first nk k-points (0 = all)")
+    ap.add_argument("--cpu-sample", type=int, default=96)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(k-points or tiles would be sharded across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synthcells
+    from paper_1602_06589_amd import Flapw
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    cell = synthcells.config(args.config, n_k=(args.nk or None))
+    nk = cell.n_k
+    gdev = [torch.as_tensor(np.ascontiguousarray(g), device="cuda") for g in cell.gvecs]
+    f_alg = [cell.flops_per_k(i) for i in range(nk)]
+    kr = cell.k_rows()
+    f_contract = [16.0 * kr * cell.n_g(i) * (cell.n_g(i) + 1.0) for i in range(nk)]
+    precs = [p.strip() for p in args.precs.split(",") if p.strip()]
+    stream = torch.cuda.current_stream()
+    print(f"# workload {cell.name}: {cell.n_atoms} atoms, {cell.n_types} types, K={kr}, {nk} k-points, "
+          f"N_G {min(cell.n_g(i) for i in range(nk))}..{max(cell.n_g(i) for i in range(nk))}, "
+          f"F_alg {sum(f_alg):.3e}", flush=True)
+
+    results, outs = {}, {}
+    with Flapw() as fl:
+        for prec in precs:
+            out = [(torch.zeros((cell.n_g(i), cell.n_g(i)), dtype=torch.complex128, device="cuda"),
+                    torch.zeros((cell.n_g(i), cell.n_g(i)), dtype=torch.complex128, device="cuda")) for i in range(nk)]
+            for _ in range(args.warmup):
+                fl.hs_generate(cell, cell.kpts, gdev, prec=prec, slices=args.slices, out=out)
+            torch.cuda.synchronize()
+            fl.profile(True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record(stream)
+            for _ in range(args.steps):
+                fl.hs_generate(cell, cell.kpts, gdev, prec=prec, slices=args.slices, out=out)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ms = e0.elapsed_time(e1) / args.steps
+            kern = {fam: fl.kernel_time(fam) for fam in ("coeffs", "tmat", "qpanel", "hs_fp64", "slice", "hs_split")}
+            fl.profile(False)
+            n_l, k_ms = kern[KERNEL[prec]]
+            achieved = sum(f_contract) * args.steps / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
+            results[prec] = {
+                "ms_per_step": ms, "wall_s": wall, "ms_per_kpoint": ms / nk,
+                "tflops": sum(f_alg) / (ms * 1e-3) / 1e12,
+                "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kern.items() if v[0]},
+                "launches_per_step": {k: v[0] // args.steps for k, v in kern.items() if v[0]},
+                "contraction_tflops": achieved,
+            }
+            print(f"# {prec}: {ms:.2f} ms/step, {results[prec]['tflops']:.2f} TFLOP/s, kernels "
+                  f"{json.dumps(results[prec]['kernels_ms_per_step'])}", flush=True)
+            outs[prec] = ([o[0] for o in out], [o[1] for o in out])
+
+        base, errs = (None, {})
+        if not args.no_cpu_baseline:
+            base, errs = cpu_baseline_leg(cell, {p: (outs[p][0][0], outs[p][1][0]) for p in precs}, args.cpu_sample)
+            for p in precs:
+                results[p]["rel_err"] = errs[p]
+
+    head = precs[0]
+    r = results[head]
+    n_launch = max(1, r["launches_per_step"].get(KERNEL[head], 1))
+    k_ms = r["kernels_ms_per_step"].get(KERNEL[head], 0.0) / n_launch
+    achieved = r["contraction_tflops"]
+    traffic = read_traffic(head, cell.name)
+    roof = {"bound": "mfma", "kernel": KERNEL[head], "achieved": achieved, "peak": PEAKS[head], "unit": "TFLOP/s",
+            "frac": (achieved / PEAKS[head]) if achieved else None, "traffic": traffic,
+            "avg_launch_ms": k_ms, "launches_per_step": n_launch,
+            "flops_per_launch": sum(f_contract) / n_launch}
+    line = {
+        "metric": "H+S gen time/k-point & TFLOP/s: split-prec vs FP64 MFMA at ≤1e-10 rel err",
+        "value": r["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "bf16": "bf16", "i8": "i8"}[head], "data": "synthetic",
+        "config": {"workload": cell.name, "n_atoms": cell.n_atoms, "n_types": cell.n_types, "K": kr,
+                   "lmax": int(cell.lmax.max()), "lpot": cell.lpot, "n_kpoints": nk,
+                   "n_g": [cell.n_g(i) for i in range(nk)], "path": head, "slices": args.slices},
+        "ms_per_kpoint": r["ms_per_kpoint"],
+        "roofline": roof,
+        "cpu_baseline": base,
+        "paths": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -168,6 +168,15 @@ flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const i
                                flapw_z *const *H, flapw_z *const *S, const long *ldh, flapw_prec prec, int slices,
                                flapw_stream stream);
 
+/* Kernel timing for profiling (off by default).  While enabled, the library records a pair of
+ * HIP events on the launch stream around every launch of its kernels.  flapw_profile_query
+ * waits for the recorded events of one kernel family and returns the number of launches and
+ * their summed duration in milliseconds since the last flapw_profile_enable(h, 1).
+ * Families: "coeffs", "tmat", "qpanel", "repack", "hs_fp64", "slice", "hs_split".
+ * Errors: FLAPW_ERR_ARG for an unknown family or NULL output pointer. */
+flapw_status flapw_profile_enable(flapw_handle h, int on);
+flapw_status flapw_profile_query(flapw_handle h, const char *family, int *launches, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

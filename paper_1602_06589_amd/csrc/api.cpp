@@ -248,6 +248,7 @@ flapw_status build_T_impl(flapw_handle h, const flapw_radial *rad, const flapw_p
     flapw_status st = upload(h, h->gaunt, hb, s);
     if (st != FLAPW_OK) return st;
     unsigned char *base = (unsigned char *)h->gaunt.p;
+    ProfScope prof(h, "tmat", s);
     hipError_t e = launch_legendre_table(lt, nq, (const double *)(base + oz), (double *)(base + oth), s);
     if (e != hipSuccess) return dev_fail(h, e, "legendre table kernel");
     e = launch_tmat(rad->n_types, (const int *)(base + ol), ls, pot->lpot, nq, (const double *)(base + ow),
@@ -295,6 +296,7 @@ flapw_status run_contraction(flapw_handle h, const Layout &L, const std::vector<
         flapw_status st = upload(h, h->tiles, hb, s);
         if (st != FLAPW_OK) return st;
         unsigned char *base = (unsigned char *)h->tiles.p;
+        ProfScope prof(h, "hs_fp64", s);
         hipError_t e = launch_hs_fp64((const ProblemDev *)(base + op), (const TileDev *)(base + ot), (int)tiles.size(), s);
         if (e != hipSuccess) return dev_fail(h, e, "S/H FP64 kernel");
         return FLAPW_OK;
@@ -330,6 +332,11 @@ flapw_status flapw_destroy(flapw_handle h)
 {
     if (!h) return FLAPW_ERR_ARG;
     if (h->device >= 0) (void)hipDeviceSynchronize();
+    for (auto &p : h->prof) {
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    for (auto e : h->spare_events) (void)hipEventDestroy(e);
     h->work.release();
     h->tmat.release();
     h->tables.release();
@@ -355,6 +362,44 @@ const char *flapw_status_string(flapw_status s)
 }
 
 const char *flapw_last_error(flapw_handle h) { return h ? h->err.c_str() : "NULL handle"; }
+
+flapw_status flapw_profile_enable(flapw_handle h, int on)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    for (auto &p : h->prof) {
+        (void)hipEventSynchronize(p.second.second);
+        h->spare_events.push_back(p.second.first);
+        h->spare_events.push_back(p.second.second);
+    }
+    h->prof.clear();
+    h->profiling = on != 0 && h->device >= 0;
+    return FLAPW_OK;
+}
+
+flapw_status flapw_profile_query(flapw_handle h, const char *family, int *launches, double *total_ms)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    if (!family || !launches || !total_ms) return fail(h, FLAPW_ERR_ARG, "NULL argument");
+    static const char *known[] = {"coeffs", "tmat", "qpanel", "repack", "hs_fp64", "slice", "hs_split"};
+    bool ok = false;
+    for (const char *k : known) ok = ok || std::strcmp(k, family) == 0;
+    if (!ok) return fail(h, FLAPW_ERR_ARG, std::string("unknown kernel family ") + family);
+    int n = 0;
+    double ms = 0.0;
+    for (auto &p : h->prof) {
+        if (p.first != family) continue;
+        hipError_t e = hipEventSynchronize(p.second.second);
+        if (e != hipSuccess) return dev_fail(h, e, "event synchronize");
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, p.second.first, p.second.second);
+        if (e != hipSuccess) return dev_fail(h, e, "event elapsed time");
+        ms += t;
+        ++n;
+    }
+    *launches = n;
+    *total_ms = ms;
+    return FLAPW_OK;
+}
 
 long long flapw_workspace_bytes(flapw_handle h)
 {
@@ -384,6 +429,7 @@ flapw_status flapw_coeffs(flapw_handle h, const double *k, int n_g, const double
     if ((st = upload(h, h->tables, hb, s)) != FLAPW_OK) return st;
     unsigned char *base = (unsigned char *)h->tables.p;
     const double pref = 4.0 * kPi / std::sqrt(at->omega);
+    ProfScope prof(h, "coeffs", s);
     hipError_t e = launch_coeffs(k, n_g, n_g, g, (const AtomDev *)(base + oa), at->n_atoms, (const TypeDev *)(base + ot),
                                  rad->n_types, pref, (double2 *)A, (double2 *)B, ld, 0, 0, s);
     if (e != hipSuccess) return dev_fail(h, e, "coefficient kernel");
@@ -451,11 +497,17 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
     const size_t orow = put(hb, L.atom_row.data(), L.atom_row.size());
     if ((st = upload(h, h->tables, hb, s)) != FLAPW_OK) return st;
     unsigned char *base = (unsigned char *)h->tables.p;
-    e = launch_repack((const double2 *)A, (const double2 *)B, lda, n_g, nullptr, 0, (const long long *)(base + osrc), P,
+    {
+        ProfScope prof(h, "repack", s);
+        e = launch_repack((const double2 *)A, (const double2 *)B, lda, n_g, nullptr, 0, (const long long *)(base + osrc), P,
                       L.kp2, (int)L.kp2, (int)np, s);
+    }
     if (e != hipSuccess) return dev_fail(h, e, "repack kernel");
-    e = launch_qpanel((const double2 *)T, ldt, ldt * ldt, (const int *)(base + oty), (const int *)(base + onl),
-                      (const long long *)(base + orow), at->n_atoms, P, Q, L.kp2, (int)np, s);
+    {
+        ProfScope prof(h, "qpanel", s);
+        e = launch_qpanel((const double2 *)T, ldt, ldt * ldt, (const int *)(base + oty), (const int *)(base + onl),
+                          (const long long *)(base + orow), at->n_atoms, P, Q, L.kp2, (int)np, s);
+    }
     if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
     ProblemDev pd{P, Q, (const double *)(base + od), (double2 *)H, (double2 *)S, L.kp2, ldh, n_g, (int)L.kp2};
     std::vector<ProblemDev> probs{pd};
@@ -530,12 +582,18 @@ flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const i
             double2 *P = (double2 *)((unsigned char *)h->work.p + off);
             double2 *Q = P + L.kp2 * np;
             off += need[i];
-            e = launch_coeffs(k + 3 * i, n_g[i], (int)np, g[i], (const AtomDev *)(base + oa), at->n_atoms,
-                              (const TypeDev *)(base + ot), rad->n_types, pref, P, P, L.kp2, 2 * L.k, L.kp2, s);
+            {
+                ProfScope prof(h, "coeffs", s);
+                e = launch_coeffs(k + 3 * i, n_g[i], (int)np, g[i], (const AtomDev *)(base + oa), at->n_atoms,
+                                  (const TypeDev *)(base + ot), rad->n_types, pref, P, P, L.kp2, 2 * L.k, L.kp2, s);
+            }
             if (e != hipSuccess) return dev_fail(h, e, "coefficient kernel");
-            e = launch_qpanel((const double2 *)h->tmat.p, ldt, ldt * ldt, (const int *)(base + oty),
-                              (const int *)(base + onl), (const long long *)(base + orow), at->n_atoms, P, Q, L.kp2,
-                              (int)np, s);
+            {
+                ProfScope prof(h, "qpanel", s);
+                e = launch_qpanel((const double2 *)h->tmat.p, ldt, ldt * ldt, (const int *)(base + oty),
+                                  (const int *)(base + onl), (const long long *)(base + orow), at->n_atoms, P, Q,
+                                  L.kp2, (int)np, s);
+            }
             if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
             probs.push_back(ProblemDev{P, Q, (const double *)(base + od), (double2 *)H[i], (double2 *)S[i], L.kp2,
                                        (long long)ldh[i], n_g[i], (int)L.kp2});

@@ -61,6 +61,10 @@ struct flapw_context {
     flapw::DevBuf sdesc;       // split precision: descriptors
     std::vector<unsigned char> host_tables, host_gaunt, host_tiles, host_sdesc;
     std::vector<long long> host_src;
+    // profiling: event pairs per kernel family, recorded while `profiling` is set
+    bool profiling = false;
+    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> prof;
+    std::vector<hipEvent_t> spare_events;
 };
 
 namespace flapw {
@@ -97,6 +101,37 @@ inline flapw_status upload(flapw_handle h, DevBuf &dst, const std::vector<unsign
     if (e != hipSuccess) return dev_fail(h, e, "uploading descriptors");
     return FLAPW_OK;
 }
+
+// Records an event pair around a launch when profiling is on:  ProfScope p(h, "name", s); launch...
+struct ProfScope {
+    flapw_handle h;
+    hipStream_t s;
+    hipEvent_t e1 = nullptr;
+    ProfScope(flapw_handle h_, const char *family, hipStream_t s_) : h(h_), s(s_)
+    {
+        if (!h || !h->profiling) return;
+        hipEvent_t e0 = take(), e = take();
+        if (!e0 || !e) return;
+        (void)hipEventRecord(e0, s);
+        e1 = e;
+        h->prof.push_back({family, {e0, e1}});
+    }
+    ~ProfScope()
+    {
+        if (e1) (void)hipEventRecord(e1, s);
+    }
+    hipEvent_t take()
+    {
+        if (!h->spare_events.empty()) {
+            hipEvent_t e = h->spare_events.back();
+            h->spare_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
 
 // split precision (split.hip)
 flapw_status split_contraction(flapw_handle h, long long kp2, const std::vector<ProblemDev> &probs,

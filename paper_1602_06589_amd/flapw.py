@@ -33,7 +33,8 @@ _STATUS = {0: "FLAPW_OK", -1: "FLAPW_ERR_ARG", -2: "FLAPW_ERR_WRONSKIAN", -3: "F
            -4: "FLAPW_ERR_NOMEM", -5: "FLAPW_ERR_DEVICE", -6: "FLAPW_ERR_UNSUPPORTED"}
 
 EXPORTS = ["flapw_create", "flapw_destroy", "flapw_status_string", "flapw_last_error", "flapw_workspace_bytes",
-           "flapw_coeffs", "flapw_build_T", "flapw_hs_contract", "flapw_hs_generate"]
+           "flapw_coeffs", "flapw_build_T", "flapw_hs_contract", "flapw_hs_generate", "flapw_profile_enable",
+           "flapw_profile_query"]
 
 
 class FlapwError(RuntimeError):
@@ -81,6 +82,8 @@ def load_library(path: str = LIB_PATH):
         lib.flapw_build_T.argtypes = [P, P, P, P, L, P]
         lib.flapw_hs_contract.argtypes = [P, I, P, P, P, P, L, P, L, P, P, L, I, I, P]
         lib.flapw_hs_generate.argtypes = [P, I, P, P, P, P, P, P, P, P, P, I, I, P]
+        lib.flapw_profile_enable.argtypes = [P, I]
+        lib.flapw_profile_query.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_double)]
         for f in EXPORTS:
             getattr(lib, f).restype = getattr(lib, f).restype or ctypes.c_int
         _lib = lib
@@ -152,6 +155,17 @@ class Flapw:
         if st != 0:
             msg = self._lib.flapw_last_error(self._h).decode() if self._h else ""
             raise FlapwError(st, msg)
+
+    def profile(self, on: bool = True):
+        """Start (or stop) recording HIP events around every kernel launch; resets the record."""
+        self._check(self._lib.flapw_profile_enable(self._h, int(bool(on))))
+
+    def kernel_time(self, family: str):
+        """(launches, total milliseconds) of a kernel family since profile(True)."""
+        n = ctypes.c_int()
+        ms = ctypes.c_double()
+        self._check(self._lib.flapw_profile_query(self._h, family.encode(), ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     @property
     def workspace_bytes(self) -> int:
