@@ -103,7 +103,21 @@ def main():
     ap.add_argument("--nk", type=int, default=0, help="use only the first nk k-points (0 = all)")
     ap.add_argument("--cpu-sample", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (calibrates the "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counters against known bytes) and exit")
     args = ap.parse_args()
+
+    if args.copy_calib:
+        import torch
+        n = args.copy_calib * (1 << 20)
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_read": n, "copy_calib_bytes_written": n, "launches": 3}))
+        return
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "

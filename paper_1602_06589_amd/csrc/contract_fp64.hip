@@ -12,10 +12,11 @@
 // Both kernels compute C = X^H Y on 64 x 64 complex tiles with v_mfma_f64_16x16x4f64.  A complex
 // product uses four real products (Re = Xr.Yr + Xi.Yi, Im = Xr.Yi - Xi.Yr).  Operands are
 // column-major with the contraction index contiguous, so a 16-row stage of one column is one
-// 256-byte segment; stages are double-buffered in LDS as planar [k][column] arrays of doubles,
-// which is the layout the MFMA operands read (lane l takes row k = l/16, column l%16).
-// Four waves each own a 32 x 32 quadrant (2 x 2 MFMA blocks); the accumulator of block (m, n)
-// holds rows l/16 + 4r, column l%16 in register r of lane l.
+// 256-byte segment; stages are double-buffered in LDS as [column][k] complex panels padded to
+// 17 slots per column, so that the MFMA operand reads (lane l: row k = l/16, column l%16, one
+// 16-byte {re, im} read) and the staging writes are both free of bank conflicts.
+// Each wave owns a 32 x 32 quadrant (2 x 2 MFMA blocks); the accumulator of block (m, n) holds
+// rows l/16 + 4r, column l%16 in register r of lane l.
 #include "common.hpp"
 
 namespace flapw {
@@ -23,48 +24,78 @@ namespace flapw {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+// Operand pointers are read from descriptors, so the compiler cannot infer that they point to
+// global memory; the address-space qualifier makes it emit global (not flat) loads, whose
+// completion is tracked apart from LDS traffic.  (The host compilation pass only parses.)
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const double2 __attribute__((address_space(1))) gdouble2;
+typedef const double __attribute__((address_space(1))) gdouble;
+#else
+typedef const double2 gdouble2;
+typedef const double gdouble;
+#endif
 
 constexpr int kThreads = 256;
-constexpr int kLW = kTile;                  // LDS row width (doubles)
+constexpr int kSlot = kKTile + 1;           // complex slots per column in LDS (one pad slot)
 
 __device__ __forceinline__ v4d mfma(double a, double b, v4d c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// C += X^H Y over one LDS stage for a wave's 2x2 blocks; acc[0] = Re, acc[1] = Im.
-__device__ __forceinline__ void stage_mma(const double (*xr)[kLW], const double (*xi)[kLW], const double (*yr)[kLW],
-                                          const double (*yi)[kLW], int wm, int wn, int lane, v4d (*acc)[2][2])
+// One LDS stage of C += X^H Y for a wave's 2 x 2 blocks and NY right operands sharing X.
+// LDS panels are [column][k] complex; lane l reads row k = ks + l/16 of column base + l%16.
+// acc[y][0] = Re, acc[y][1] = Im.  The first sweep issues Xr.Yr and Xr.Yi for every block, the
+// second Xi.Yi and -Xi.Yr, so no two consecutive MFMAs use the same accumulator.
+template <int NY, int KS0 = 0, int KSTEP = 4>
+__device__ __forceinline__ void stage_mma(const double2 (*X)[kSlot], const double2 (*Y0)[kSlot],
+                                          const double2 (*Y1)[kSlot], int wm, int wn, int lane,
+                                          v4d (&acc)[NY][2][2][2])
 {
+    const int c = lane & 15;
 #pragma unroll
-    for (int ks = 0; ks < kKTile; ks += 4) {
-        const int kr = ks + (lane >> 4), cc = lane & 15;
-        double ar[2], ai[2], br[2], bi[2];
+    for (int ks = KS0; ks < kKTile; ks += KSTEP) {
+        const int k = ks + (lane >> 4);
+        double2 x[2], y[NY][2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            ar[q] = xr[kr][wm + q * 16 + cc];
-            ai[q] = xi[kr][wm + q * 16 + cc];
-            br[q] = yr[kr][wn + q * 16 + cc];
-            bi[q] = yi[kr][wn + q * 16 + cc];
+            x[q] = X[wm + q * 16 + c][k];
+            y[0][q] = Y0[wn + q * 16 + c][k];
+            if constexpr (NY > 1) y[NY - 1][q] = Y1[wn + q * 16 + c][k];
         }
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+        for (int v = 0; v < NY; ++v)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni) {
-                acc[0][mi][ni] = mfma(ar[mi], br[ni], acc[0][mi][ni]);
-                acc[0][mi][ni] = mfma(ai[mi], bi[ni], acc[0][mi][ni]);
-                acc[1][mi][ni] = mfma(ar[mi], bi[ni], acc[1][mi][ni]);
-                acc[1][mi][ni] = mfma(-ai[mi], br[ni], acc[1][mi][ni]);
-            }
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni) {
+                    acc[v][0][mi][ni] = mfma(x[mi].x, y[v][ni].x, acc[v][0][mi][ni]);
+                    acc[v][1][mi][ni] = mfma(x[mi].x, y[v][ni].y, acc[v][1][mi][ni]);
+                }
+#pragma unroll
+        for (int v = 0; v < NY; ++v)
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni) {
+                    acc[v][0][mi][ni] = mfma(x[mi].y, y[v][ni].y, acc[v][0][mi][ni]);
+                    acc[v][1][mi][ni] = mfma(-x[mi].y, y[v][ni].x, acc[v][1][mi][ni]);
+                }
     }
 }
 
 struct HsSmem {
-    double v[2][6][kKTile][kLW];            // [buffer][Lre, Lim, Rre, Rim, Qre, Qim][k][col]
+    double2 v[2][3][kTile][kSlot];          // [buffer][left P, right d.P, right Q][column][k]
 };
 
-__global__ __launch_bounds__(kThreads, 1) void hs_fp64_kernel(const ProblemDev *__restrict__ probs,
-                                                              const TileDev *__restrict__ tiles)
+constexpr int kHsThreads = 512;             // 8 waves: two per SIMD, splitting each stage's k-steps
+
+// Eight waves: wave w owns quadrant (w & 3) of the 64 x 64 tile (2 x 2 MFMA blocks) and the
+// k-steps {0, 8} (w < 4) or {4, 12} (w >= 4) of every 16-row stage, so two waves per SIMD
+// keep the FP64 matrix core busy across barriers and LDS waits.  Their partial sums are
+// added through LDS at the end; waves 0-3 then store S, waves 4-7 store H.
+__global__ __launch_bounds__(kHsThreads, 1) void hs_fp64_kernel(const ProblemDev *__restrict__ probs,
+                                                                const TileDev *__restrict__ tiles)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     HsSmem &sm = *reinterpret_cast<HsSmem *>(smem_raw);
@@ -72,83 +103,114 @@ __global__ __launch_bounds__(kThreads, 1) void hs_fp64_kernel(const ProblemDev *
     const TileDev td = tiles[blockIdx.x];
     const ProblemDev pb = probs[td.prob];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int quad = wave & 3, khalf = wave >> 2;
+    const int wm = (quad >> 1) * 32, wn = (quad & 1) * 32;
     const long long i0 = (long long)td.ti * kTile, j0 = (long long)td.tj * kTile;
 
-    const int lc = tid >> 2, lk = (tid & 3) * 4;       // loader: column lc, rows lk..lk+3 of a stage
-    const double2 *gL = pb.P + (i0 + lc) * pb.ldp + lk;
-    const double2 *gR = pb.P + (j0 + lc) * pb.ldp + lk;
-    const double2 *gQ = pb.Q + (j0 + lc) * pb.ldp + lk;
-    const double *gd = pb.d + lk;
+    const int lc = tid >> 3, lk = (tid & 7) * 2;       // loader: column lc, rows lk, lk+1 of a stage
+    gdouble2 *gL = (gdouble2 *)pb.P + (i0 + lc) * pb.ldp + lk;
+    gdouble2 *gR = (gdouble2 *)pb.P + (j0 + lc) * pb.ldp + lk;
+    gdouble2 *gQ = (gdouble2 *)pb.Q + (j0 + lc) * pb.ldp + lk;
+    gdouble *gd = (gdouble *)pb.d + lk;
 
-    v4d acc[4][2][2];                                  // S re, S im, H re, H im
+    v4d acc[2][2][2][2];                               // [S, H][re, im][mi][ni]
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int n = 0; n < 2; ++n) acc[a][m][n] = (v4d){0.0, 0.0, 0.0, 0.0};
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int n = 0; n < 2; ++n) acc[a][b][m][n] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-    double2 rl[4], rr[4], rq[4];
-    double rd[4];
-    auto gload = [&](int kt) {
-        const long long off = (long long)kt * kKTile;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            rl[r] = gL[off + r];
-            rr[r] = gR[off + r];
-            rq[r] = gQ[off + r];
-            rd[r] = gd[off + r];
-        }
-    };
-    auto sstore = [&](int b) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            sm.v[b][0][lk + r][lc] = rl[r].x;
-            sm.v[b][1][lk + r][lc] = rl[r].y;
-            sm.v[b][2][lk + r][lc] = rr[r].x * rd[r];
-            sm.v[b][3][lk + r][lc] = rr[r].y * rd[r];
-            sm.v[b][4][lk + r][lc] = rq[r].x;
-            sm.v[b][5][lk + r][lc] = rq[r].y;
-        }
-    };
+    // Stage loads go through registers (issued one stage ahead) and are written to LDS after the
+    // MFMAs of the current stage.  Plain scalars, not captured arrays, keep them in registers.
+    double2 l0, l1, r0, r1, q0, q1;
+    double d0, d1;
+#define HS_LOAD(kt)                                                     \
+    do {                                                                \
+        const long long off_ = (long long)(kt) * kKTile;                \
+        l0 = gL[off_]; l1 = gL[off_ + 1];                               \
+        r0 = gR[off_]; r1 = gR[off_ + 1];                               \
+        q0 = gQ[off_]; q1 = gQ[off_ + 1];                               \
+        d0 = gd[off_]; d1 = gd[off_ + 1];                               \
+    } while (0)
+#define HS_STORE(b)                                                                              \
+    do {                                                                                         \
+        double2 *sl_ = &sm.v[b][0][lc][lk], *sr_ = &sm.v[b][1][lc][lk], *sq_ = &sm.v[b][2][lc][lk]; \
+        sl_[0] = l0; sl_[1] = l1;                                                                \
+        sr_[0] = make_double2(r0.x * d0, r0.y * d0); sr_[1] = make_double2(r1.x * d1, r1.y * d1); \
+        sq_[0] = q0; sq_[1] = q1;                                                                \
+    } while (0)
 
     const int nkt = pb.kp2 / kKTile;
-    gload(0);
-    sstore(0);
+    HS_LOAD(0);
+    HS_STORE(0);
     __syncthreads();
     for (int kt = 0; kt < nkt; ++kt) {
         const int b = kt & 1;
-        if (kt + 1 < nkt) gload(kt + 1);
-        stage_mma(sm.v[b][0], sm.v[b][1], sm.v[b][2], sm.v[b][3], wm, wn, lane, &acc[0]);
-        stage_mma(sm.v[b][0], sm.v[b][1], sm.v[b][4], sm.v[b][5], wm, wn, lane, &acc[2]);
-        if (kt + 1 < nkt) sstore(b ^ 1);
+        if (kt + 1 < nkt) HS_LOAD(kt + 1);
+        if (khalf == 0) stage_mma<2, 0, 8>(sm.v[b][0], sm.v[b][1], sm.v[b][2], wm, wn, lane, acc);
+        else            stage_mma<2, 4, 8>(sm.v[b][0], sm.v[b][1], sm.v[b][2], wm, wn, lane, acc);
+        if (kt + 1 < nkt) HS_STORE(b ^ 1);
+        __syncthreads();
+    }
+#undef HS_LOAD
+#undef HS_STORE
+
+    // add the two halves: S partials of waves 4-7 to waves 0-3, then H partials the other way
+    double *xch = reinterpret_cast<double *>(smem_raw);   // [quadrant][32 values][64 lanes]
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+        const int mat = round;                              // 0: S, 1: H
+        const bool sender = (round == 0) ? (khalf == 1) : (khalf == 0);
+        if (sender) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            xch[((quad * 32) + ((c * 2 + mi) * 2 + ni) * 4 + r) * 64 + lane] = acc[mat][c][mi][ni][r];
+        }
+        __syncthreads();
+        if (!sender) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            acc[mat][c][mi][ni][r] += xch[((quad * 32) + ((c * 2 + mi) * 2 + ni) * 4 + r) * 64 + lane];
+        }
         __syncthreads();
     }
 
     // epilogue: upper triangle (row <= col < n); diagonal imaginary part set to zero
+    const int mat = khalf;                                  // waves 0-3 store S, waves 4-7 store H
+    double2 *out = mat == 0 ? pb.S : pb.H;
 #pragma unroll
-    for (int mat = 0; mat < 2; ++mat) {
-        double2 *out = mat == 0 ? pb.S : pb.H;
+    for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+        for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const long long row = i0 + wm + mi * 16 + (lane >> 4) + 4 * r;
-                    const long long col = j0 + wn + ni * 16 + (lane & 15);
-                    if (row <= col && col < pb.n) {
-                        const double re = acc[2 * mat][mi][ni][r];
-                        const double im = row == col ? 0.0 : acc[2 * mat + 1][mi][ni][r];
-                        out[col * pb.ldh + row] = make_double2(re, im);
-                    }
+            for (int r = 0; r < 4; ++r) {
+                const long long row = i0 + wm + mi * 16 + (lane >> 4) + 4 * r;
+                const long long col = j0 + wn + ni * 16 + (lane & 15);
+                if (row <= col && col < pb.n) {
+                    const double re = mat == 0 ? acc[0][0][mi][ni][r] : acc[1][0][mi][ni][r];
+                    const double im = mat == 0 ? acc[0][1][mi][ni][r] : acc[1][1][mi][ni][r];
+                    out[col * pb.ldh + row] = make_double2(re, row == col ? 0.0 : im);
                 }
-    }
+            }
 }
 
 struct QSmem {
-    double v[2][4][kKTile][kLW];            // [buffer][Xre, Xim, Yre, Yim][k][col]
+    double2 v[2][2][kTile][kSlot];          // [buffer][X = T columns, Y = P rows of the atom][column][k]
 };
 
 // grid: x = column tile, y = atom, z = row tile of the atom's 2NL rows
@@ -167,54 +229,53 @@ __global__ __launch_bounds__(kThreads, 1) void qpanel_kernel(const double2 *__re
     const int r0 = blockIdx.z * kTile;
     if (r0 >= m2) return;
     const long long prow = atom_row[a];
-    const double2 *Ta = T + (long long)atom_type[a] * tstride;
     const long long c0 = (long long)blockIdx.x * kTile;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int lc = tid >> 2, lk = (tid & 3) * 4;
     const bool xcol_ok = (r0 + lc) < m2;
-    const double2 *gX = Ta + (long long)(xcol_ok ? r0 + lc : 0) * ldt + lk;
-    const double2 *gY = P + (c0 + lc) * ldp + prow + lk;
+    gdouble2 *gX = (gdouble2 *)T + (long long)atom_type[a] * tstride + (long long)(xcol_ok ? r0 + lc : 0) * ldt + lk;
+    gdouble2 *gY = (gdouble2 *)P + (c0 + lc) * ldp + prow + lk;
 
-    v4d acc[2][2][2];
+    v4d acc[1][2][2][2];
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
-            for (int n = 0; n < 2; ++n) acc[q][m][n] = (v4d){0.0, 0.0, 0.0, 0.0};
+            for (int n = 0; n < 2; ++n) acc[0][q][m][n] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-    double2 rx[4], ry[4];
-    auto gload = [&](int kt) {
-        const int k0 = kt * kKTile + lk;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const bool ok = (k0 + r) < m2;
-            rx[r] = (ok && xcol_ok) ? gX[kt * kKTile + r] : make_double2(0.0, 0.0);
-            ry[r] = ok ? gY[kt * kKTile + r] : make_double2(0.0, 0.0);
-        }
-    };
-    auto sstore = [&](int b) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            sm.v[b][0][lk + r][lc] = rx[r].x;
-            sm.v[b][1][lk + r][lc] = rx[r].y;
-            sm.v[b][2][lk + r][lc] = ry[r].x;
-            sm.v[b][3][lk + r][lc] = ry[r].y;
-        }
-    };
+    double2 x0, x1, x2, x3, y0, y1, y2, y3;
+#define Q_LOAD(kt)                                                           \
+    do {                                                                     \
+        const int k0_ = (kt) * kKTile + lk, o_ = (kt) * kKTile;              \
+        const double2 z_ = make_double2(0.0, 0.0);                           \
+        x0 = z_; x1 = z_; x2 = z_; x3 = z_; y0 = z_; y1 = z_; y2 = z_; y3 = z_; \
+        if (k0_ + 0 < m2) { y0 = gY[o_ + 0]; if (xcol_ok) x0 = gX[o_ + 0]; } \
+        if (k0_ + 1 < m2) { y1 = gY[o_ + 1]; if (xcol_ok) x1 = gX[o_ + 1]; } \
+        if (k0_ + 2 < m2) { y2 = gY[o_ + 2]; if (xcol_ok) x2 = gX[o_ + 2]; } \
+        if (k0_ + 3 < m2) { y3 = gY[o_ + 3]; if (xcol_ok) x3 = gX[o_ + 3]; } \
+    } while (0)
+#define Q_STORE(b)                                                              \
+    do {                                                                        \
+        double2 *sx_ = &sm.v[b][0][lc][lk], *sy_ = &sm.v[b][1][lc][lk];         \
+        sx_[0] = x0; sx_[1] = x1; sx_[2] = x2; sx_[3] = x3;                     \
+        sy_[0] = y0; sy_[1] = y1; sy_[2] = y2; sy_[3] = y3;                     \
+    } while (0)
     const int nkt = (m2 + kKTile - 1) / kKTile;
-    gload(0);
-    sstore(0);
+    Q_LOAD(0);
+    Q_STORE(0);
     __syncthreads();
     for (int kt = 0; kt < nkt; ++kt) {
         const int b = kt & 1;
-        if (kt + 1 < nkt) gload(kt + 1);
-        stage_mma(sm.v[b][0], sm.v[b][1], sm.v[b][2], sm.v[b][3], wm, wn, lane, &acc[0]);
-        if (kt + 1 < nkt) sstore(b ^ 1);
+        if (kt + 1 < nkt) Q_LOAD(kt + 1);
+        stage_mma<1>(sm.v[b][0], sm.v[b][1], sm.v[b][1], wm, wn, lane, acc);
+        if (kt + 1 < nkt) Q_STORE(b ^ 1);
         __syncthreads();
     }
+#undef Q_LOAD
+#undef Q_STORE
     // T is Hermitian, so X^H Y with X = T is T P.
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
@@ -224,7 +285,7 @@ __global__ __launch_bounds__(kThreads, 1) void qpanel_kernel(const double2 *__re
             for (int r = 0; r < 4; ++r) {
                 const int row = r0 + wm + mi * 16 + (lane >> 4) + 4 * r;
                 const long long col = c0 + wn + ni * 16 + (lane & 15);
-                if (row < m2) Q[col * ldp + prow + row] = make_double2(acc[0][mi][ni][r], acc[1][mi][ni][r]);
+                if (row < m2) Q[col * ldp + prow + row] = make_double2(acc[0][0][mi][ni][r], acc[0][1][mi][ni][r]);
             }
 }
 
@@ -256,7 +317,7 @@ hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_t
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(hs_fp64_kernel, dim3(n_tiles), dim3(kThreads), sizeof(HsSmem), s, probs, tiles);
+    hipLaunchKernelGGL(hs_fp64_kernel, dim3(n_tiles), dim3(kHsThreads), sizeof(HsSmem), s, probs, tiles);
     return hipGetLastError();
 }
 
@@ -271,11 +332,7 @@ hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, con
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const int rt = (2 * (FLAPW_LMAX_CAP + 1) * (FLAPW_LMAX_CAP + 1) + kTile - 1) / kTile;
-    (void)rt;
-    int max_rows = 0;
-    (void)max_rows;
-    // row tiles: enough for the largest atom block, passed by the caller through tstride's matrix size
+    // row tiles: enough for the largest atom block (2 NL <= ldt)
     const int row_tiles = (int)((ldt + kTile - 1) / kTile);
     hipLaunchKernelGGL(qpanel_kernel, dim3(np / kTile, n_atoms, row_tiles), dim3(kThreads), sizeof(QSmem), s, T, ldt,
                        tstride, atom_type, atom_nl2, atom_row, P, Q, ldp);
