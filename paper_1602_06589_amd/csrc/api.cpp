@@ -261,8 +261,9 @@ flapw_status build_T_impl(flapw_handle h, const flapw_radial *rad, const flapw_p
 
 // Upper-triangle tile list of several problems, ordered in bands of kBand tile rows (so that
 // work-groups running together share operand panels) and remapped so that each of the eight
-// XCDs (work-group b runs on XCD b % 8) receives a contiguous run of that order.
-void build_tiles(const std::vector<int> &np_tiles, std::vector<TileDev> &out)
+// XCDs (work-group b runs on XCD b % 8) receives a contiguous run of that order.  With mats = 2
+// (split precision) every (ti, tj) gives an S tile and an H tile next to each other.
+void build_tiles(const std::vector<int> &np_tiles, int mats, std::vector<TileDev> &out)
 {
     constexpr int kBand = 4;
     std::vector<TileDev> order;
@@ -270,7 +271,8 @@ void build_tiles(const std::vector<int> &np_tiles, std::vector<TileDev> &out)
         const int nt = np_tiles[p];
         for (int b0 = 0; b0 < nt; b0 += kBand)
             for (int tj = b0; tj < nt; ++tj)
-                for (int ti = b0; ti < std::min(b0 + kBand, tj + 1); ++ti) order.push_back(TileDev{p, ti, tj, 0});
+                for (int ti = b0; ti < std::min(b0 + kBand, tj + 1); ++ti)
+                    for (int m = 0; m < mats; ++m) order.push_back(TileDev{p, ti, tj, m});
     }
     const int n = (int)order.size();
     out.resize(n);
@@ -281,27 +283,75 @@ void build_tiles(const std::vector<int> &np_tiles, std::vector<TileDev> &out)
     for (int b = 0; b < n; ++b) out[b] = order[start[b % 8] + b / 8];
 }
 
-// Contraction stage for a batch of problems whose P (and Q) are already in the work buffer.
-flapw_status run_contraction(flapw_handle h, const Layout &L, const std::vector<ProblemDev> &probs_in,
-                             const std::vector<int> &npt, size_t tab_base, flapw_prec prec, int slices, hipStream_t s)
+int default_slices(flapw_prec prec) { return prec == FLAPW_PREC_SPLIT_I8 ? 6 : 5; }
+
+// Digit storage of one problem inside a digit buffer.
+struct DigitArea {
+    int8_t *L, *RS, *RH;
+    int *eL, *eRS, *eRH;
+};
+
+long long digit_area_bytes(long long kp2, long long np, int s)
 {
-    (void)tab_base;
+    const long long one = round_up(2LL * s * kp2 * np, 256);
+    return 3 * one + 3 * round_up(np * 4, 256);
+}
+
+DigitArea digit_area(void *base, long long kp2, long long np, int s)
+{
+    const long long one = round_up(2LL * s * kp2 * np, 256);
+    const long long ex = round_up(np * 4, 256);
+    unsigned char *b = (unsigned char *)base;
+    return DigitArea{(int8_t *)b, (int8_t *)(b + one), (int8_t *)(b + 2 * one), (int *)(b + 3 * one),
+                     (int *)(b + 3 * one + ex), (int *)(b + 3 * one + 2 * ex)};
+}
+
+flapw_status slice_problem(flapw_handle h, const ProblemDev &pb, long long np, int s, const DigitArea &da,
+                           hipStream_t st)
+{
+    ProfScope prof(h, "slice", st);
+    hipError_t e = launch_split_slice(pb.P, pb.Q, pb.d, pb.ldp, pb.kp2, (int)np, s, da.eL, da.eRS, da.eRH, da.L,
+                                      da.RS, da.RH, st);
+    if (e != hipSuccess) return dev_fail(h, e, "digit slicing kernels");
+    return FLAPW_OK;
+}
+
+flapw_status run_split(flapw_handle h, const std::vector<SplitProblemDev> &probs, const std::vector<int> &npt, int s,
+                       hipStream_t st)
+{
     std::vector<TileDev> tiles;
-    build_tiles(npt, tiles);
-    if (prec == FLAPW_PREC_FP64) {
-        auto &hb = h->host_tiles;
-        hb.clear();
-        const size_t op = put(hb, probs_in.data(), probs_in.size());
-        const size_t ot = put(hb, tiles.data(), tiles.size());
-        flapw_status st = upload(h, h->tiles, hb, s);
-        if (st != FLAPW_OK) return st;
-        unsigned char *base = (unsigned char *)h->tiles.p;
-        ProfScope prof(h, "hs_fp64", s);
-        hipError_t e = launch_hs_fp64((const ProblemDev *)(base + op), (const TileDev *)(base + ot), (int)tiles.size(), s);
-        if (e != hipSuccess) return dev_fail(h, e, "S/H FP64 kernel");
-        return FLAPW_OK;
-    }
-    return split_contraction(h, L.kp2, probs_in, tiles, prec, slices, s);
+    build_tiles(npt, 2, tiles);
+    auto &hb = h->host_sdesc;
+    hb.clear();
+    const size_t op = put(hb, probs.data(), probs.size());
+    const size_t ot = put(hb, tiles.data(), tiles.size());
+    flapw_status r = upload(h, h->sdesc, hb, st);
+    if (r != FLAPW_OK) return r;
+    unsigned char *base = (unsigned char *)h->sdesc.p;
+    ProfScope prof(h, "hs_split", st);
+    hipError_t e = launch_split_contract((const SplitProblemDev *)(base + op), (const TileDev *)(base + ot),
+                                         (int)tiles.size(), s, st);
+    if (e != hipSuccess) return dev_fail(h, e, "S/H split-precision kernel");
+    return FLAPW_OK;
+}
+
+// FP64 contraction stage for a batch of problems whose P and Q are in the work buffer.
+flapw_status run_fp64(flapw_handle h, const std::vector<ProblemDev> &probs_in, const std::vector<int> &npt,
+                      hipStream_t s)
+{
+    std::vector<TileDev> tiles;
+    build_tiles(npt, 1, tiles);
+    auto &hb = h->host_tiles;
+    hb.clear();
+    const size_t op = put(hb, probs_in.data(), probs_in.size());
+    const size_t ot = put(hb, tiles.data(), tiles.size());
+    flapw_status st = upload(h, h->tiles, hb, s);
+    if (st != FLAPW_OK) return st;
+    unsigned char *base = (unsigned char *)h->tiles.p;
+    ProfScope prof(h, "hs_fp64", s);
+    hipError_t e = launch_hs_fp64((const ProblemDev *)(base + op), (const TileDev *)(base + ot), (int)tiles.size(), s);
+    if (e != hipSuccess) return dev_fail(h, e, "S/H FP64 kernel");
+    return FLAPW_OK;
 }
 
 }  // namespace
@@ -461,6 +511,9 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
     if (prec != FLAPW_PREC_FP64 && prec != FLAPW_PREC_SPLIT_BF16 && prec != FLAPW_PREC_SPLIT_I8)
         return fail(h, FLAPW_ERR_ARG, "unknown precision");
     if (slices < 0 || slices > FLAPW_SLICES_CAP) return fail(h, FLAPW_ERR_ARG, "slices out of range");
+    if (prec == FLAPW_PREC_SPLIT_I8 && slices != 0 && (slices < 3 || slices > 6))
+        return fail(h, FLAPW_ERR_UNSUPPORTED, "int8 split precision supports 3..6 digits");
+    if (prec == FLAPW_PREC_SPLIT_BF16) return fail(h, FLAPW_ERR_UNSUPPORTED, "bf16 split precision is not built");
     flapw_status st = check_radial(h, rad);
     if (st != FLAPW_OK) return st;
     if ((st = check_atoms(h, at, rad, false)) != FLAPW_OK) return st;
@@ -510,9 +563,15 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
     }
     if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
     ProblemDev pd{P, Q, (const double *)(base + od), (double2 *)H, (double2 *)S, L.kp2, ldh, n_g, (int)L.kp2};
-    std::vector<ProblemDev> probs{pd};
     std::vector<int> npt{(int)(np / kTile)};
-    return run_contraction(h, L, probs, npt, 0, prec, slices, s);
+    if (prec == FLAPW_PREC_FP64) return run_fp64(h, {pd}, npt, s);
+    const int sl = slices ? slices : default_slices(prec);
+    e = h->digits.ensure((size_t)digit_area_bytes(L.kp2, np, sl));
+    if (e != hipSuccess) return dev_fail(h, e, "allocating digit buffer");
+    const DigitArea da = digit_area(h->digits.p, L.kp2, np, sl);
+    if ((st = slice_problem(h, pd, np, sl, da, s)) != FLAPW_OK) return st;
+    SplitProblemDev sp{da.L, da.RS, da.RH, da.eL, da.eRS, da.eRH, (double2 *)H, (double2 *)S, ldh, n_g, (int)L.kp2};
+    return run_split(h, {sp}, npt, sl, s);
 }
 
 flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const int *n_g, const double *const *g,
@@ -526,6 +585,9 @@ flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const i
     if (prec != FLAPW_PREC_FP64 && prec != FLAPW_PREC_SPLIT_BF16 && prec != FLAPW_PREC_SPLIT_I8)
         return fail(h, FLAPW_ERR_ARG, "unknown precision");
     if (slices < 0 || slices > FLAPW_SLICES_CAP) return fail(h, FLAPW_ERR_ARG, "slices out of range");
+    if (prec == FLAPW_PREC_SPLIT_I8 && slices != 0 && (slices < 3 || slices > 6))
+        return fail(h, FLAPW_ERR_UNSUPPORTED, "int8 split precision supports 3..6 digits");
+    if (prec == FLAPW_PREC_SPLIT_BF16) return fail(h, FLAPW_ERR_UNSUPPORTED, "bf16 split precision is not built");
     for (int i = 0; i < n_k; ++i) {
         if (n_g[i] < 1) return fail(h, FLAPW_ERR_ARG, "n_g must be >= 1");
         if (!g[i] || !H[i] || !S[i]) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
@@ -558,30 +620,46 @@ flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const i
     unsigned char *base = (unsigned char *)h->tables.p;
     const double pref = 4.0 * kPi / std::sqrt(at->omega);
 
-    // memory batches of k-points: P and Q of every k-point of a batch stay resident
+    // Memory batches of k-points.  FP64: the P and Q panels of every k-point of a batch stay
+    // resident for one grouped contraction launch.  Split precision: P and Q of one k-point at a
+    // time are cut into digits (the FP64 panels are reused), and the digits of every k-point of a
+    // batch stay resident for the grouped launch.
     size_t free_b = 0, total_b = 0;
     e = hipMemGetInfo(&free_b, &total_b);
     if (e != hipSuccess) return dev_fail(h, e, "hipMemGetInfo");
     double frac = 0.55;
     if (const char *env = std::getenv("FLAPW_WORK_FRACTION")) frac = std::atof(env);
-    const size_t budget = (size_t)(frac * (double)total_b);
+    const bool split = prec != FLAPW_PREC_FP64;
+    const int sl = split ? (slices ? slices : default_slices(prec)) : 0;
+    long long np_max = 0;
+    for (int i = 0; i < n_k; ++i) np_max = std::max(np_max, round_up(n_g[i], kTile));
+    const size_t panel_one = (size_t)2 * L.kp2 * np_max * sizeof(double2);
+    size_t budget = (size_t)(frac * (double)total_b);
     std::vector<size_t> need(n_k);
-    for (int i = 0; i < n_k; ++i) need[i] = (size_t)2 * L.kp2 * round_up(n_g[i], kTile) * sizeof(double2);
+    for (int i = 0; i < n_k; ++i) {
+        const long long np = round_up(n_g[i], kTile);
+        need[i] = split ? (size_t)digit_area_bytes(L.kp2, np, sl) : (size_t)2 * L.kp2 * np * sizeof(double2);
+    }
+    if (split) {
+        e = h->work.ensure(panel_one);
+        if (e != hipSuccess) return dev_fail(h, e, "allocating work buffer");
+        budget = budget > panel_one ? budget - panel_one : 0;
+    }
     int i0 = 0;
     while (i0 < n_k) {
         int i1 = i0;
         size_t tot = 0;
         while (i1 < n_k && (i1 == i0 || tot + need[i1] <= budget)) tot += need[i1++];
-        e = h->work.ensure(tot);
-        if (e != hipSuccess) return dev_fail(h, e, "allocating work buffer");
+        e = (split ? h->digits : h->work).ensure(tot);
+        if (e != hipSuccess) return dev_fail(h, e, split ? "allocating digit buffer" : "allocating work buffer");
         std::vector<ProblemDev> probs;
+        std::vector<SplitProblemDev> sprobs;
         std::vector<int> npt;
         size_t off = 0;
         for (int i = i0; i < i1; ++i) {
             const long long np = round_up(n_g[i], kTile);
-            double2 *P = (double2 *)((unsigned char *)h->work.p + off);
+            double2 *P = (double2 *)((unsigned char *)h->work.p + (split ? 0 : off));
             double2 *Q = P + L.kp2 * np;
-            off += need[i];
             {
                 ProfScope prof(h, "coeffs", s);
                 e = launch_coeffs(k + 3 * i, n_g[i], (int)np, g[i], (const AtomDev *)(base + oa), at->n_atoms,
@@ -595,11 +673,21 @@ flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const i
                                   L.kp2, (int)np, s);
             }
             if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
-            probs.push_back(ProblemDev{P, Q, (const double *)(base + od), (double2 *)H[i], (double2 *)S[i], L.kp2,
-                                       (long long)ldh[i], n_g[i], (int)L.kp2});
+            const ProblemDev pd{P, Q, (const double *)(base + od), (double2 *)H[i], (double2 *)S[i], L.kp2,
+                                (long long)ldh[i], n_g[i], (int)L.kp2};
+            if (split) {
+                const DigitArea da = digit_area((unsigned char *)h->digits.p + off, L.kp2, np, sl);
+                if ((st = slice_problem(h, pd, np, sl, da, s)) != FLAPW_OK) return st;
+                sprobs.push_back(SplitProblemDev{da.L, da.RS, da.RH, da.eL, da.eRS, da.eRH, (double2 *)H[i],
+                                                 (double2 *)S[i], (long long)ldh[i], n_g[i], (int)L.kp2});
+            } else {
+                probs.push_back(pd);
+            }
+            off += need[i];
             npt.push_back((int)(np / kTile));
         }
-        if ((st = run_contraction(h, L, probs, npt, 0, prec, slices, s)) != FLAPW_OK) return st;
+        st = split ? run_split(h, sprobs, npt, sl, s) : run_fp64(h, probs, npt, s);
+        if (st != FLAPW_OK) return st;
         i0 = i1;
     }
     return FLAPW_OK;

@@ -52,18 +52,17 @@ struct ProblemDev {
     int kp2;
 };
 
-// Split-precision operands of one k-point (see split.hip).
+// Split-precision operands of one k-point (digit layout described in split.hip).
 struct SplitProblemDev {
-    const void *L;        // left digits  [slice][plane re/im][np][kp2b]   (bytes per digit: esz)
-    const void *R;        // right digits for S (the d-weighted P)
-    const void *RQ;       // right digits for H (Q)
-    const int *eL;        // per-column exponents of the left operand  [np]
+    const void *L;        // left digits (from P)
+    const void *R;        // right digits of S (from the d-weighted P)
+    const void *RQ;       // right digits of H (from Q)
+    const int *eL;        // per-column scale exponents, np entries each
     const int *eR;
     const int *eRQ;
     double2 *H;
     double2 *S;
     long long ldh;
-    long long plane;      // elements per (slice, re/im) plane = np * kp2
     int n;
     int kp2;              // contraction rows (padded)
 };
@@ -72,7 +71,7 @@ struct TileDev {
     int prob;             // problem index
     int ti;               // tile row
     int tj;               // tile column (ti <= tj)
-    int pad;
+    int pad;              // split precision: 0 = S tile, 1 = H tile
 };
 
 // kernel launchers (return hipError_t of the launch)
@@ -95,6 +94,13 @@ hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_t
 hipError_t launch_repack(const double2 *A, const double2 *B, long long lda, int n_g, const AtomDev *atoms,
                          int n_atoms, const long long *src_off, double2 *P, long long ldp, int kp2, int np,
                          hipStream_t s);
+
+long long split_digit_bytes(long long kp2, long long np, int s);
+hipError_t launch_split_slice(const double2 *P, const double2 *Q, const double *d, long long ld, int kp2, int np,
+                              int slices, int *eL, int *eRS, int *eRH, int8_t *L, int8_t *RS, int8_t *RH,
+                              hipStream_t s);
+hipError_t launch_split_contract(const SplitProblemDev *probs, const TileDev *tiles, int n_tiles, int slices,
+                                 hipStream_t s);
 
 constexpr int kTile = 64;     // output tile edge (complex elements) of the contraction kernels
 constexpr int kKTile = 16;    // contraction rows per pipeline stage (FP64 kernels)

@@ -134,8 +134,6 @@ struct ProfScope {
 };
 
 // split precision (split.hip)
-flapw_status split_contraction(flapw_handle h, long long kp2, const std::vector<ProblemDev> &probs,
-                               const std::vector<TileDev> &tiles, flapw_prec prec, int slices, hipStream_t s);
 void split_release(flapw_handle h);
 long long split_bytes(flapw_handle h);
 
