@@ -244,6 +244,7 @@ __global__ __launch_bounds__(256, 1) void hs_split_i8_kernel(const SplitProblemD
     __syncthreads();
 
     const int half_a = lane >> 5, col = lane & 31;
+    const unsigned negmask = half_a ? 0xffffffffu : 0u;          // lanes 32-63 carry Xi
     for (int st = 0; st < nst; ++st) {
         const int b = st & 1;
         if (st + 1 < nst) SPLIT_LOAD(st + 1);
@@ -252,21 +253,34 @@ __global__ __launch_bounds__(256, 1) void hs_split_i8_kernel(const SplitProblemD
         for (int kk = 0; kk < kChunksPerStage; ++kk) {
             const unsigned char *lrun = stage + wmb * SM::kRunBytes + kk * S * 1024 + half_a * 512 + col * 16;
             const unsigned char *rrun = stage + (2 + wnb) * SM::kRunBytes + kk * S * 1024 + col * 16;
+            // all A reads and the first B pair issued back to back; the negation of the
+            // imaginary half (lanes 32-63) is a lane select, not a branch
             v4i a_re[S], a_im[S];
 #pragma unroll
+            for (int p = 0; p < S; ++p) a_re[p] = *reinterpret_cast<const v4i *>(lrun + p * 1024);
+            v4i b_re = *reinterpret_cast<const v4i *>(rrun + half_a * 512);
+            v4i b_im = *reinterpret_cast<const v4i *>(rrun + (1 - half_a) * 512);
+#pragma unroll
             for (int p = 0; p < S; ++p) {
-                a_re[p] = *reinterpret_cast<const v4i *>(lrun + p * 1024);
-                a_im[p] = half_a ? neg_i8x16(a_re[p]) : a_re[p];
+                const v4i n = neg_i8x16(a_re[p]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    a_im[p][i] = (int)(((unsigned)n[i] & negmask) | ((unsigned)a_re[p][i] & ~negmask));
             }
 #pragma unroll
             for (int q = 0; q < S; ++q) {
-                const v4i b_re = *reinterpret_cast<const v4i *>(rrun + q * 1024 + half_a * 512);
-                const v4i b_im = *reinterpret_cast<const v4i *>(rrun + q * 1024 + (1 - half_a) * 512);
+                v4i nb_re = b_re, nb_im = b_im;
+                if (q + 1 < S) {                 // B fragments of the next q, read ahead
+                    nb_re = *reinterpret_cast<const v4i *>(rrun + (q + 1) * 1024 + half_a * 512);
+                    nb_im = *reinterpret_cast<const v4i *>(rrun + (q + 1) * 1024 + (1 - half_a) * 512);
+                }
 #pragma unroll
                 for (int p = 0; p + q < S; ++p) {
                     acc_re[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_re[p], b_re, acc_re[p + q], 0, 0, 0);
                     acc_im[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_im[p], b_im, acc_im[p + q], 0, 0, 0);
                 }
+                b_re = nb_re;
+                b_im = nb_im;
             }
         }
         if (st + 1 < nst) SPLIT_STORE(b ^ 1);
