@@ -274,11 +274,13 @@ __global__ __launch_bounds__(256, 1) void hs_split_i8_kernel(const SplitProblemD
                     nb_re = *reinterpret_cast<const v4i *>(rrun + (q + 1) * 1024 + half_a * 512);
                     nb_im = *reinterpret_cast<const v4i *>(rrun + (q + 1) * 1024 + (1 - half_a) * 512);
                 }
+                // Re products first: they do not wait for the negated fragments
 #pragma unroll
-                for (int p = 0; p + q < S; ++p) {
+                for (int p = 0; p + q < S; ++p)
                     acc_re[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_re[p], b_re, acc_re[p + q], 0, 0, 0);
+#pragma unroll
+                for (int p = 0; p + q < S; ++p)
                     acc_im[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_im[p], b_im, acc_im[p + q], 0, 0, 0);
-                }
                 b_re = nb_re;
                 b_im = nb_im;
             }
