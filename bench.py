@@ -126,7 +126,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(k-points or tiles would be sharded across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+              "(k-points, being independent, would be divided among GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -7,7 +7,7 @@
  * Everything is FP64 (complex128 where complex), written as the paper's sums with no
  * blocking or reordering beyond what is stated next to each function.
  *
- * Conventions (the paper leaves them open; the same readings are listed in the design doc):
+ * Conventions (the paper leaves them open):
  *   - complex spherical harmonics, orthonormal, with the Condon-Shortley phase,
  *     Y_{l,-m} = (-1)^m conj(Y_{l,m});
  *   - L = l*l + l + m;

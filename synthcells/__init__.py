@@ -25,8 +25,10 @@ Conventions (readings of points the paper leaves open):
   * (u, u', udot, udot') of one (type, l) are redrawn until |W| >= 0.05 with
     W = udot u' - u udot'.
 
-The five named workloads follow the paper's sizes (N_G ~ 50-80 per atom, l_max <= 10)
-and are described in the design doc's input recipe.
+The five named workloads follow the paper's sizes (N_G ~ 50-80 per atom, l_max <= 10,
+section 2.3): a 2-atom cell with N_G = 300, a 64-atom rock-salt supercell with N_G = 3000, a
+256-atom fcc cell with l_max = 10 and N_G = 6000, a 32-atom cell with 64 k-points of uneven
+N_G in [2000, 4500], and a 512-atom cell with 4 k-points of N_G in [11000, 12500].
 """
 from __future__ import annotations
 
