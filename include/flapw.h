@@ -168,11 +168,49 @@ flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const i
                                flapw_z *const *H, flapw_z *const *S, const long *ldh, flapw_prec prec, int slices,
                                flapw_stream stream);
 
+/* Captured generation.  flapw_plan_create validates like flapw_hs_generate, allocates device
+ * buffers owned by the plan (not shared with the handle), uploads every descriptor, and records
+ * the whole generation (T, and per k-point coefficients, panels, digit slicing, then the grouped
+ * contraction launches) into a HIP graph.  flapw_plan_launch replays it on `stream`; every replay
+ * recomputes H and S from the same inputs (the device G lists are read at replay time, the host
+ * descriptors -- k, atoms, radial data, potential -- are those given at creation).  The plan
+ * keeps the output pointers; the caller keeps the outputs and the G lists alive while the plan
+ * exists.  Replays of one plan must not overlap.  A plan is used from one thread at a time.
+ * Errors: as flapw_hs_generate; FLAPW_ERR_DEVICE when capture or instantiation fails. */
+typedef struct flapw_plan_s *flapw_plan;
+flapw_status flapw_plan_create(flapw_handle h, int n_k, const double *k, const int *n_g, const double *const *g,
+                               const flapw_atoms *at, const flapw_radial *rad, const flapw_potential *pot,
+                               flapw_z *const *H, flapw_z *const *S, const long *ldh, flapw_prec prec, int slices,
+                               flapw_plan *plan);
+flapw_status flapw_plan_launch(flapw_plan plan, flapw_stream stream);
+flapw_status flapw_plan_destroy(flapw_plan plan);
+
+/* Autotuner.  Chooses, for one k-point (k, n_g G vectors, device list g), the digit count of
+ * the split path and the tile band of the contraction (the number of tile rows one band of the
+ * launch order walks; neighbouring work-groups of a band share their row panel in L2).
+ *   digits: the first min(n_g, 1024) columns are generated with FP64 and with 3, 4, 5, 6 digits;
+ *           the smallest digit count whose relative Frobenius errors of H and S (upper
+ *           triangles, against that FP64 result) are both <= tol / 4 is chosen.  FP64: 0.
+ *   band:   a prefix of at most 8192 tiles of the contraction of the whole k-point is timed
+ *           with HIP events for bands 1, 2, 4, 8, 16; the fastest is chosen.
+ * The choice is stored in the handle under (prec, padded contraction rows of the atom set) and
+ * used by later flapw_hs_contract / flapw_hs_generate / flapw_plan_create calls with slices = 0
+ * (band: every call) whose atom set gives the same key.
+ * Outputs: *slices, *band; digit_err[4] (errors for 3..6 digits, NaN where not evaluated) and
+ * band_ms[5] (prefix times for bands 1, 2, 4, 8, 16) when not NULL.
+ * Runs synchronously on the null stream and allocates temporary device memory for two n_g x n_g
+ * outputs (freed before returning).  Errors: as flapw_hs_generate; FLAPW_ERR_ARG for tol <= 0;
+ * FLAPW_ERR_UNSUPPORTED when no digit count meets tol (digit_err is still filled). */
+flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
+                        const flapw_radial *rad, const flapw_potential *pot, flapw_prec prec, double tol, int *slices,
+                        int *band, double *digit_err, double *band_ms);
+
 /* Kernel timing for profiling (off by default).  While enabled, the library records a pair of
  * HIP events on the launch stream around every launch of its kernels.  flapw_profile_query
  * waits for the recorded events of one kernel family and returns the number of launches and
  * their summed duration in milliseconds since the last flapw_profile_enable(h, 1).
- * Families: "coeffs", "tmat", "qpanel", "repack", "hs_fp64", "slice", "hs_split".
+ * Families: "coeffs", "tmat", "qpanel", "repack", "hs_fp64", "slice", "hs_split", "graph"
+ * (a whole flapw_plan_launch; kernels inside a graph are not timed one by one).
  * Errors: FLAPW_ERR_ARG for an unknown family or NULL output pointer. */
 flapw_status flapw_profile_enable(flapw_handle h, int on);
 flapw_status flapw_profile_query(flapw_handle h, const char *family, int *launches, double *total_ms);

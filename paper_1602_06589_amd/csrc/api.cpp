@@ -221,51 +221,72 @@ void gauss_legendre(int n, std::vector<double> &z, std::vector<double> &w)
     }
 }
 
+// Host preparation of the T build: quadrature nodes and weights, integrals, E_l, ||udot||^2,
+// l_max, and room for the Legendre table, packed into one buffer for one upload.
+struct GauntPlan {
+    int lt = 0, nq = 0, ls = 0, lpot = 0, n_types = 0;
+    size_t oz = 0, ow = 0, o1 = 0, o2 = 0, o3 = 0, o4 = 0, oe = 0, on = 0, ol = 0, oth = 0;
+};
+
+void prepare_T(const flapw_radial *rad, const flapw_potential *pot, std::vector<unsigned char> &hb, GauntPlan &gp)
+{
+    int lm = 0;
+    for (int t = 0; t < rad->n_types; ++t) lm = std::max(lm, rad->lmax[t]);
+    gp.lt = std::max(lm, pot->lpot);
+    gp.nq = lm + pot->lpot + 2;                  // exact for polynomial degree <= 2 lmax + lpot
+    gp.ls = rad->lstride;
+    gp.lpot = pot->lpot;
+    gp.n_types = rad->n_types;
+    std::vector<double> z, w;
+    gauss_legendre(gp.nq, z, w);
+    const int nlp = (pot->lpot + 1) * (pot->lpot + 1);
+    const size_t ni = (size_t)rad->n_types * gp.ls * gp.ls * nlp;
+    hb.clear();
+    gp.oz = put(hb, z.data(), z.size());
+    gp.ow = put(hb, w.data(), w.size());
+    gp.o1 = put(hb, pot->i_uu, ni);
+    gp.o2 = put(hb, pot->i_ud, ni);
+    gp.o3 = put(hb, pot->i_du, ni);
+    gp.o4 = put(hb, pot->i_dd, ni);
+    gp.oe = put(hb, rad->e_l, (size_t)rad->n_types * gp.ls);
+    gp.on = put(hb, rad->ud_norm2, (size_t)rad->n_types * gp.ls);
+    gp.ol = put(hb, rad->lmax, (size_t)rad->n_types);
+    gp.oth = round_up(hb.size(), 256);
+    const size_t nth = (size_t)(gp.lt + 1) * (gp.lt + 2) / 2 * gp.nq;
+    hb.resize(gp.oth + nth * sizeof(double));
+}
+
+flapw_status launch_T(flapw_handle h, const unsigned char *base, const GauntPlan &gp, double2 *T, long long ldt,
+                      hipStream_t s)
+{
+    ProfScope prof(h, "tmat", s);
+    hipError_t e = launch_legendre_table(gp.lt, gp.nq, (const double *)(base + gp.oz), (double *)(base + gp.oth), s);
+    if (e != hipSuccess) return dev_fail(h, e, "legendre table kernel");
+    e = launch_tmat(gp.n_types, (const int *)(base + gp.ol), gp.ls, gp.lpot, gp.nq, (const double *)(base + gp.ow),
+                    (const double *)(base + gp.oth), (const double *)(base + gp.o1), (const double *)(base + gp.o2),
+                    (const double *)(base + gp.o3), (const double *)(base + gp.o4), (const double *)(base + gp.oe),
+                    (const double *)(base + gp.on), T, ldt, s);
+    if (e != hipSuccess) return dev_fail(h, e, "T assembly kernel");
+    return FLAPW_OK;
+}
+
 // T of all types into dev (ldt x ldt each).
 flapw_status build_T_impl(flapw_handle h, const flapw_radial *rad, const flapw_potential *pot, double2 *T, long long ldt,
                           hipStream_t s)
 {
-    int lm = 0;
-    for (int t = 0; t < rad->n_types; ++t) lm = std::max(lm, rad->lmax[t]);
-    const int lt = std::max(lm, pot->lpot);
-    const int nq = lm + pot->lpot + 2;            // exact for polynomial degree <= 2 lmax + lpot
-    std::vector<double> z, w;
-    gauss_legendre(nq, z, w);
-    const int ls = rad->lstride, nlp = (pot->lpot + 1) * (pot->lpot + 1);
-    const size_t ni = (size_t)rad->n_types * ls * ls * nlp;
-    auto &hb = h->host_gaunt;
-    hb.clear();
-    const size_t oz = put(hb, z.data(), z.size());
-    const size_t ow = put(hb, w.data(), w.size());
-    const size_t o1 = put(hb, pot->i_uu, ni), o2 = put(hb, pot->i_ud, ni), o3 = put(hb, pot->i_du, ni),
-                 o4 = put(hb, pot->i_dd, ni);
-    const size_t oe = put(hb, rad->e_l, (size_t)rad->n_types * ls);
-    const size_t on = put(hb, rad->ud_norm2, (size_t)rad->n_types * ls);
-    const size_t ol = put(hb, rad->lmax, (size_t)rad->n_types);
-    const size_t oth = round_up(hb.size(), 256);
-    const size_t nth = (size_t)(lt + 1) * (lt + 2) / 2 * nq;
-    hb.resize(oth + nth * sizeof(double));
-    flapw_status st = upload(h, h->gaunt, hb, s);
+    GauntPlan gp;
+    prepare_T(rad, pot, h->host_gaunt, gp);
+    flapw_status st = upload(h, h->gaunt, h->host_gaunt, s);
     if (st != FLAPW_OK) return st;
-    unsigned char *base = (unsigned char *)h->gaunt.p;
-    ProfScope prof(h, "tmat", s);
-    hipError_t e = launch_legendre_table(lt, nq, (const double *)(base + oz), (double *)(base + oth), s);
-    if (e != hipSuccess) return dev_fail(h, e, "legendre table kernel");
-    e = launch_tmat(rad->n_types, (const int *)(base + ol), ls, pot->lpot, nq, (const double *)(base + ow),
-                    (const double *)(base + oth), (const double *)(base + o1), (const double *)(base + o2),
-                    (const double *)(base + o3), (const double *)(base + o4), (const double *)(base + oe),
-                    (const double *)(base + on), T, ldt, s);
-    if (e != hipSuccess) return dev_fail(h, e, "T assembly kernel");
-    return FLAPW_OK;
+    return launch_T(h, (const unsigned char *)h->gaunt.p, gp, T, ldt, s);
 }
 
 // Upper-triangle tile list of several problems, ordered in bands of kBand tile rows (so that
 // work-groups running together share operand panels) and remapped so that each of the eight
 // XCDs (work-group b runs on XCD b % 8) receives a contiguous run of that order.  With mats = 2
 // (split precision) every (ti, tj) gives an S tile and an H tile next to each other.
-void build_tiles(const std::vector<int> &np_tiles, int mats, std::vector<TileDev> &out)
+void build_tiles(const std::vector<int> &np_tiles, int mats, std::vector<TileDev> &out, int kBand = 4)
 {
-    constexpr int kBand = 4;
     std::vector<TileDev> order;
     for (int p = 0; p < (int)np_tiles.size(); ++p) {
         const int nt = np_tiles[p];
@@ -284,6 +305,28 @@ void build_tiles(const std::vector<int> &np_tiles, int mats, std::vector<TileDev
 }
 
 int default_slices(flapw_prec prec) { return prec == FLAPW_PREC_SPLIT_I8 ? 6 : 5; }
+
+const flapw_context::Tuned *find_tuned(flapw_handle h, flapw_prec prec, long long kp2)
+{
+    for (const auto &t : h->tuned)
+        if (t.prec == (int)prec && t.kp2 == kp2) return &t;
+    return nullptr;
+}
+
+// slices == 0: the tuned digit count for (prec, kp2), else the library default
+int effective_slices(flapw_handle h, flapw_prec prec, long long kp2, int slices)
+{
+    if (prec == FLAPW_PREC_FP64) return 0;
+    if (slices) return slices;
+    const auto *t = find_tuned(h, prec, kp2);
+    return t && t->slices ? t->slices : default_slices(prec);
+}
+
+int effective_band(flapw_handle h, flapw_prec prec, long long kp2)
+{
+    const auto *t = find_tuned(h, prec, kp2);
+    return t ? t->band : 4;
+}
 
 // Digit storage of one problem inside a digit buffer.
 struct DigitArea {
@@ -317,10 +360,10 @@ flapw_status slice_problem(flapw_handle h, const ProblemDev &pb, long long np, i
 }
 
 flapw_status run_split(flapw_handle h, const std::vector<SplitProblemDev> &probs, const std::vector<int> &npt, int s,
-                       hipStream_t st)
+                       int band, hipStream_t st)
 {
     std::vector<TileDev> tiles;
-    build_tiles(npt, 2, tiles);
+    build_tiles(npt, 2, tiles, band);
     auto &hb = h->host_sdesc;
     hb.clear();
     const size_t op = put(hb, probs.data(), probs.size());
@@ -336,11 +379,11 @@ flapw_status run_split(flapw_handle h, const std::vector<SplitProblemDev> &probs
 }
 
 // FP64 contraction stage for a batch of problems whose P and Q are in the work buffer.
-flapw_status run_fp64(flapw_handle h, const std::vector<ProblemDev> &probs_in, const std::vector<int> &npt,
+flapw_status run_fp64(flapw_handle h, const std::vector<ProblemDev> &probs_in, const std::vector<int> &npt, int band,
                       hipStream_t s)
 {
     std::vector<TileDev> tiles;
-    build_tiles(npt, 1, tiles);
+    build_tiles(npt, 1, tiles, band);
     auto &hb = h->host_tiles;
     hb.clear();
     const size_t op = put(hb, probs_in.data(), probs_in.size());
@@ -353,6 +396,292 @@ flapw_status run_fp64(flapw_handle h, const std::vector<ProblemDev> &probs_in, c
     if (e != hipSuccess) return dev_fail(h, e, "S/H FP64 kernel");
     return FLAPW_OK;
 }
+
+
+// ----------------------------------------------------------------------------- S/H generation plans
+
+// Everything one S/H generation over n_k k-points launches.  prepare_generate validates nothing
+// (callers do), sizes and allocates the device buffers, and uploads every descriptor;
+// enqueue_generate only launches kernels, so it can also be captured into a HIP graph.
+struct GenBatch {
+    int i0 = 0, i1 = 0;          // k-points [i0, i1)
+    size_t o_probs = 0, o_tiles = 0;
+    int n_tiles = 0;
+};
+
+struct GenPlan {
+    Layout L;
+    int n_k = 0;
+    bool split = false;
+    int sl = 0, band = 4;
+    long long ldt = 0;
+    double pref = 0.0;
+    int n_atoms = 0, n_types = 0;
+    std::vector<double> kv;
+    std::vector<const double *> g;
+    std::vector<int> ng;
+    std::vector<long long> np;
+    std::vector<size_t> off;     // per k-point: byte offset of its P/Q (FP64) or digits (split)
+    GauntPlan gp;
+    size_t oa = 0, ot = 0, od = 0, oty = 0, onl = 0, orow = 0;
+    std::vector<GenBatch> batches;
+    double2 *T = nullptr;
+    unsigned char *tables = nullptr, *gaunt = nullptr, *desc = nullptr, *work = nullptr, *digits = nullptr;
+};
+
+struct GenBuffers {
+    DevBuf *tmat, *tables, *gaunt, *desc, *work, *digits;
+    std::vector<unsigned char> *h_tables, *h_gaunt, *h_desc;
+};
+
+flapw_status put_device(flapw_handle h, DevBuf &dst, const std::vector<unsigned char> &src, hipStream_t s, bool sync)
+{
+    hipError_t e = dst.ensure(src.size());
+    if (e != hipSuccess) return dev_fail(h, e, "allocating descriptor buffer");
+    e = sync ? hipMemcpy(dst.p, src.data(), src.size(), hipMemcpyHostToDevice)
+             : hipMemcpyAsync(dst.p, src.data(), src.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return dev_fail(h, e, "uploading descriptors");
+    return FLAPW_OK;
+}
+
+flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const int *n_g, const double *const *g,
+                              const flapw_atoms *at, const flapw_radial *rad, const flapw_potential *pot,
+                              flapw_z *const *H, flapw_z *const *S, const long *ldh, flapw_prec prec, int slices,
+                              int band, GenBuffers &b, GenPlan &p, hipStream_t s, bool sync_upload)
+{
+    Layout &L = p.L;
+    build_layout(at, rad, true, L);
+    p.n_k = n_k;
+    p.n_atoms = at->n_atoms;
+    p.n_types = rad->n_types;
+    p.split = prec != FLAPW_PREC_FP64;
+    p.sl = effective_slices(h, prec, L.kp2, slices);
+    p.band = band ? band : effective_band(h, prec, L.kp2);
+    p.ldt = 2LL * L.nlmax;
+    p.pref = 4.0 * kPi / std::sqrt(at->omega);
+    p.kv.assign(k, k + 3 * (size_t)n_k);
+    p.g.assign(g, g + n_k);
+    p.ng.assign(n_g, n_g + n_k);
+    p.np.resize(n_k);
+    for (int i = 0; i < n_k; ++i) p.np[i] = round_up(n_g[i], kTile);
+
+    hipError_t e = b.tmat->ensure((size_t)rad->n_types * p.ldt * p.ldt * sizeof(double2));
+    if (e != hipSuccess) return dev_fail(h, e, "allocating T");
+    p.T = (double2 *)b.tmat->p;
+    prepare_T(rad, pot, *b.h_gaunt, p.gp);
+    flapw_status st = put_device(h, *b.gaunt, *b.h_gaunt, s, sync_upload);
+    if (st != FLAPW_OK) return st;
+    p.gaunt = (unsigned char *)b.gaunt->p;
+
+    auto &ht = *b.h_tables;
+    ht.clear();
+    p.oa = put(ht, L.atoms.data(), L.atoms.size());
+    p.ot = put(ht, L.types.data(), L.types.size());
+    p.od = put(ht, L.d.data(), L.d.size());
+    p.oty = put(ht, L.atom_type.data(), L.atom_type.size());
+    p.onl = put(ht, L.atom_nl2.data(), L.atom_nl2.size());
+    p.orow = put(ht, L.atom_row.data(), L.atom_row.size());
+    if ((st = put_device(h, *b.tables, ht, s, sync_upload)) != FLAPW_OK) return st;
+    p.tables = (unsigned char *)b.tables->p;
+
+    // Memory batches.  FP64: P and Q of every k-point of a batch stay resident for one grouped
+    // contraction launch.  Split precision: the FP64 panels of one k-point at a time are cut into
+    // digits (the panels are reused), and the digits of every k-point of a batch stay resident.
+    size_t free_b = 0, total_b = 0;
+    e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) return dev_fail(h, e, "hipMemGetInfo");
+    double frac = 0.55;
+    if (const char *env = std::getenv("FLAPW_WORK_FRACTION")) frac = std::atof(env);
+    long long np_max = 0;
+    for (int i = 0; i < n_k; ++i) np_max = std::max(np_max, p.np[i]);
+    const size_t panel_one = (size_t)2 * L.kp2 * np_max * sizeof(double2);
+    size_t budget = (size_t)(frac * (double)total_b);
+    if (p.split) budget = budget > panel_one ? budget - panel_one : 0;
+    std::vector<size_t> need(n_k);
+    for (int i = 0; i < n_k; ++i)
+        need[i] = p.split ? (size_t)digit_area_bytes(L.kp2, p.np[i], p.sl) : (size_t)2 * L.kp2 * p.np[i] * sizeof(double2);
+    p.off.assign(n_k, 0);
+    size_t biggest = 0;
+    for (int i0 = 0; i0 < n_k;) {
+        GenBatch bt;
+        bt.i0 = i0;
+        int i1 = i0;
+        size_t tot = 0;
+        while (i1 < n_k && (i1 == i0 || tot + need[i1] <= budget)) {
+            p.off[i1] = tot;
+            tot += need[i1++];
+        }
+        bt.i1 = i1;
+        biggest = std::max(biggest, tot);
+        p.batches.push_back(bt);
+        i0 = i1;
+    }
+    if (p.split) {
+        if ((e = b.work->ensure(panel_one)) != hipSuccess) return dev_fail(h, e, "allocating work buffer");
+        if ((e = b.digits->ensure(biggest)) != hipSuccess) return dev_fail(h, e, "allocating digit buffer");
+        p.digits = (unsigned char *)b.digits->p;
+    } else {
+        if ((e = b.work->ensure(biggest)) != hipSuccess) return dev_fail(h, e, "allocating work buffer");
+    }
+    p.work = (unsigned char *)b.work->p;
+
+    // contraction descriptors of every batch
+    auto &hd = *b.h_desc;
+    hd.clear();
+    for (auto &bt : p.batches) {
+        std::vector<int> npt;
+        std::vector<ProblemDev> probs;
+        std::vector<SplitProblemDev> sprobs;
+        for (int i = bt.i0; i < bt.i1; ++i) {
+            npt.push_back((int)(p.np[i] / kTile));
+            if (p.split) {
+                const DigitArea da = digit_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl);
+                sprobs.push_back(SplitProblemDev{da.L, da.RS, da.RH, da.eL, da.eRS, da.eRH, (double2 *)H[i],
+                                                 (double2 *)S[i], (long long)ldh[i], n_g[i], (int)L.kp2});
+            } else {
+                double2 *P = (double2 *)(p.work + p.off[i]);
+                probs.push_back(ProblemDev{P, P + L.kp2 * p.np[i], (const double *)(p.tables + p.od), (double2 *)H[i],
+                                           (double2 *)S[i], L.kp2, (long long)ldh[i], n_g[i], (int)L.kp2});
+            }
+        }
+        std::vector<TileDev> tiles;
+        build_tiles(npt, p.split ? 2 : 1, tiles, p.band);
+        bt.o_probs = p.split ? put(hd, sprobs.data(), sprobs.size()) : put(hd, probs.data(), probs.size());
+        bt.o_tiles = put(hd, tiles.data(), tiles.size());
+        bt.n_tiles = (int)tiles.size();
+    }
+    if ((st = put_device(h, *b.desc, hd, s, sync_upload)) != FLAPW_OK) return st;
+    p.desc = (unsigned char *)b.desc->p;
+    return FLAPW_OK;
+}
+
+flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
+{
+    flapw_status st = launch_T(h, p.gaunt, p.gp, p.T, p.ldt, s);
+    if (st != FLAPW_OK) return st;
+    const Layout &L = p.L;
+    for (const auto &bt : p.batches) {
+        for (int i = bt.i0; i < bt.i1; ++i) {
+            double2 *P = (double2 *)(p.work + (p.split ? 0 : p.off[i]));
+            double2 *Q = P + L.kp2 * p.np[i];
+            hipError_t e;
+            {
+                ProfScope prof(h, "coeffs", s);
+                e = launch_coeffs(p.kv.data() + 3 * i, p.ng[i], (int)p.np[i], p.g[i], (const AtomDev *)(p.tables + p.oa),
+                                  p.n_atoms, (const TypeDev *)(p.tables + p.ot), p.n_types, p.pref, P, P, L.kp2,
+                                  2 * L.k, L.kp2, s);
+            }
+            if (e != hipSuccess) return dev_fail(h, e, "coefficient kernel");
+            {
+                ProfScope prof(h, "qpanel", s);
+                e = launch_qpanel(p.T, p.ldt, p.ldt * p.ldt, (const int *)(p.tables + p.oty),
+                                  (const int *)(p.tables + p.onl), (const long long *)(p.tables + p.orow), p.n_atoms, P,
+                                  Q, L.kp2, (int)p.np[i], s);
+            }
+            if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
+            if (p.split) {
+                const DigitArea da = digit_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl);
+                const ProblemDev pd{P, Q, (const double *)(p.tables + p.od), nullptr, nullptr, L.kp2, 0, p.ng[i],
+                                    (int)L.kp2};
+                if ((st = slice_problem(h, pd, p.np[i], p.sl, da, s)) != FLAPW_OK) return st;
+            }
+        }
+        hipError_t e;
+        if (p.split) {
+            ProfScope prof(h, "hs_split", s);
+            e = launch_split_contract((const SplitProblemDev *)(p.desc + bt.o_probs), (const TileDev *)(p.desc + bt.o_tiles),
+                                      bt.n_tiles, p.sl, s);
+        } else {
+            ProfScope prof(h, "hs_fp64", s);
+            e = launch_hs_fp64((const ProblemDev *)(p.desc + bt.o_probs), (const TileDev *)(p.desc + bt.o_tiles), bt.n_tiles,
+                               s);
+        }
+        if (e != hipSuccess) return dev_fail(h, e, p.split ? "S/H split-precision kernel" : "S/H FP64 kernel");
+    }
+    return FLAPW_OK;
+}
+
+flapw_status check_generate(flapw_handle h, int n_k, const double *k, const int *n_g, const double *const *g,
+                            const flapw_atoms *at, const flapw_radial *rad, const flapw_potential *pot,
+                            flapw_z *const *H, flapw_z *const *S, const long *ldh, flapw_prec prec, int slices)
+{
+    if (n_k < 1) return fail(h, FLAPW_ERR_ARG, "n_k must be >= 1");
+    if (!k || !n_g || !g || !H || !S || !ldh) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
+    if (prec != FLAPW_PREC_FP64 && prec != FLAPW_PREC_SPLIT_BF16 && prec != FLAPW_PREC_SPLIT_I8)
+        return fail(h, FLAPW_ERR_ARG, "unknown precision");
+    if (slices < 0 || slices > FLAPW_SLICES_CAP) return fail(h, FLAPW_ERR_ARG, "slices out of range");
+    if (prec == FLAPW_PREC_SPLIT_I8 && slices != 0 && (slices < 3 || slices > 6))
+        return fail(h, FLAPW_ERR_UNSUPPORTED, "int8 split precision supports 3..6 digits");
+    if (prec == FLAPW_PREC_SPLIT_BF16) return fail(h, FLAPW_ERR_UNSUPPORTED, "bf16 split precision is not built");
+    for (int i = 0; i < n_k; ++i) {
+        if (n_g[i] < 1) return fail(h, FLAPW_ERR_ARG, "n_g must be >= 1");
+        if (!g[i] || !H[i] || !S[i]) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
+        if (ldh[i] < n_g[i]) return fail(h, FLAPW_ERR_ARG, "ldh < n_g");
+    }
+    if (!finite_all(k, 3 * (size_t)n_k)) return fail(h, FLAPW_ERR_ARG, "non-finite k");
+    flapw_status st = check_radial(h, rad);
+    if (st != FLAPW_OK) return st;
+    if ((st = check_atoms(h, at, rad, true)) != FLAPW_OK) return st;
+    if ((st = check_potential(h, pot, rad)) != FLAPW_OK) return st;
+    if (h->device < 0) return fail(h, FLAPW_ERR_DEVICE, "no HIP device");
+    return FLAPW_OK;
+}
+
+
+// Times the first min(n_tiles, cap) tiles of the (single) contraction batch of a prepared plan.
+flapw_status time_contraction(flapw_handle h, const GenPlan &p, int cap, float *ms)
+{
+    const GenBatch &bt = p.batches[0];
+    const int n = std::min(bt.n_tiles, cap);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {     // first launch warms caches and code
+        e = hipEventRecord(e0, nullptr);
+        if (e == hipSuccess)
+            e = p.split ? launch_split_contract((const SplitProblemDev *)(p.desc + bt.o_probs),
+                                                (const TileDev *)(p.desc + bt.o_tiles), n, p.sl, nullptr)
+                        : launch_hs_fp64((const ProblemDev *)(p.desc + bt.o_probs), (const TileDev *)(p.desc + bt.o_tiles),
+                                         n, nullptr);
+        if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return dev_fail(h, e, "timing the contraction");
+    return FLAPW_OK;
+}
+
+// Relative Frobenius error of the upper triangles (with diagonal) of two n x n column-major matrices.
+double upper_relfro(const std::vector<double2> &got, const std::vector<double2> &ref, int n)
+{
+    double num = 0.0, den = 0.0;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i <= j; ++i) {
+            const double2 a = got[(size_t)j * n + i], b = ref[(size_t)j * n + i];
+            num += (a.x - b.x) * (a.x - b.x) + (a.y - b.y) * (a.y - b.y);
+            den += b.x * b.x + b.y * b.y;
+        }
+    return den > 0.0 ? std::sqrt(num / den) : std::sqrt(num);
+}
+
+// Device scratch of the tuner, freed on every exit path.
+struct TuneScratch {
+    std::vector<void *> ptrs;
+    hipError_t alloc(void **p, size_t bytes)
+    {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+    ~TuneScratch()
+    {
+        (void)hipDeviceSynchronize();
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+};
+
 
 }  // namespace
 
@@ -413,6 +742,84 @@ const char *flapw_status_string(flapw_status s)
 
 const char *flapw_last_error(flapw_handle h) { return h ? h->err.c_str() : "NULL handle"; }
 
+flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
+                        const flapw_radial *rad, const flapw_potential *pot, flapw_prec prec, double tol, int *slices,
+                        int *band, double *digit_err, double *band_ms)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    if (!slices || !band) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(h, FLAPW_ERR_ARG, "tol must be finite and > 0");
+    flapw_z *dummy = reinterpret_cast<flapw_z *>(&tol);       // stands in for H/S in the shared checks
+    const long ld1 = n_g;
+    flapw_status st = check_generate(h, 1, k, &n_g, &g, at, rad, pot, &dummy, &dummy, &ld1, prec, 0);
+    if (st != FLAPW_OK) return st;
+    for (int i = 0; digit_err && i < 4; ++i) digit_err[i] = std::nan("");
+    for (int i = 0; band_ms && i < 5; ++i) band_ms[i] = std::nan("");
+    const bool split = prec != FLAPW_PREC_FP64;
+    TuneScratch scratch;
+    hipError_t e;
+    int chosen = 0;
+    GenBuffers b{&h->tmat, &h->tables, &h->gaunt, &h->tiles, &h->work, &h->digits, &h->host_tables, &h->host_gaunt,
+                 &h->host_tiles};
+    if (split) {
+        // accuracy gate on the first n_acc columns (the shortest k+G), against the FP64 path
+        const int n_acc = std::min(n_g, 1024);
+        const size_t mat = (size_t)n_acc * n_acc * sizeof(double2);
+        void *buf[4];
+        for (int i = 0; i < 4; ++i)
+            if ((e = scratch.alloc(&buf[i], mat)) != hipSuccess) return dev_fail(h, e, "allocating tuner outputs");
+        std::vector<double2> Hr((size_t)n_acc * n_acc), Sr(Hr.size()), Hc(Hr.size()), Sc(Hr.size());
+        const long ldn = n_acc;
+        for (int s = 0; s <= 6; s = s ? s + 1 : 3) {          // s = 0 (FP64 reference), then 3..6 digits
+            flapw_z *Hp = (flapw_z *)buf[s ? 2 : 0], *Sp = (flapw_z *)buf[s ? 3 : 1];
+            GenPlan p;
+            st = prepare_generate(h, 1, k, &n_acc, &g, at, rad, pot, &Hp, &Sp, &ldn, s ? prec : FLAPW_PREC_FP64, s, 4, b,
+                                  p, nullptr, false);
+            if (st == FLAPW_OK) st = enqueue_generate(h, p, nullptr);
+            if (st != FLAPW_OK) return st;
+            e = hipMemcpy((s ? Hc : Hr).data(), Hp, mat, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) e = hipMemcpy((s ? Sc : Sr).data(), Sp, mat, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return dev_fail(h, e, "reading tuner outputs");
+            if (!s) continue;
+            const double err = std::max(upper_relfro(Hc, Hr, n_acc), upper_relfro(Sc, Sr, n_acc));
+            if (digit_err) digit_err[s - 3] = err;
+            if (!chosen && err <= 0.25 * tol) chosen = s;
+        }
+        if (!chosen) return fail(h, FLAPW_ERR_UNSUPPORTED, "no digit count in 3..6 meets the tolerance");
+    }
+    // tile band: time a prefix of the full contraction of this k-point with every candidate band
+    const size_t mat = (size_t)n_g * n_g * sizeof(double2);
+    void *Hb = nullptr, *Sb = nullptr;
+    if ((e = scratch.alloc(&Hb, mat)) != hipSuccess || (e = scratch.alloc(&Sb, mat)) != hipSuccess)
+        return dev_fail(h, e, "allocating tuner outputs");
+    static const int bands[5] = {1, 2, 4, 8, 16};
+    int best = 4;
+    float best_ms = 0.0f;
+    for (int i = 0; i < 5; ++i) {
+        flapw_z *Hp = (flapw_z *)Hb, *Sp = (flapw_z *)Sb;
+        GenPlan p;
+        st = prepare_generate(h, 1, k, &n_g, &g, at, rad, pot, &Hp, &Sp, &ld1, prec, chosen, bands[i], b, p, nullptr,
+                              false);
+        if (st == FLAPW_OK && i == 0) st = enqueue_generate(h, p, nullptr);   // panels / digits for the timing
+        if (st != FLAPW_OK) return st;
+        if (p.batches.size() != 1) return fail(h, FLAPW_ERR_NOMEM, "one k-point does not fit the work budget");
+        float ms = 0.0f;
+        if ((st = time_contraction(h, p, 8192, &ms)) != FLAPW_OK) return st;
+        if (band_ms) band_ms[i] = ms;
+        if (i == 0 || ms < best_ms) best_ms = ms, best = bands[i];
+    }
+    Layout L;
+    build_layout(at, rad, true, L);
+    flapw_context::Tuned t{(int)prec, L.kp2, chosen, best};
+    bool found = false;
+    for (auto &x : h->tuned)
+        if (x.prec == t.prec && x.kp2 == t.kp2) x = t, found = true;
+    if (!found) h->tuned.push_back(t);
+    *slices = chosen;
+    *band = best;
+    return FLAPW_OK;
+}
+
 flapw_status flapw_profile_enable(flapw_handle h, int on)
 {
     if (!h) return FLAPW_ERR_ARG;
@@ -430,7 +837,7 @@ flapw_status flapw_profile_query(flapw_handle h, const char *family, int *launch
 {
     if (!h) return FLAPW_ERR_ARG;
     if (!family || !launches || !total_ms) return fail(h, FLAPW_ERR_ARG, "NULL argument");
-    static const char *known[] = {"coeffs", "tmat", "qpanel", "repack", "hs_fp64", "slice", "hs_split"};
+    static const char *known[] = {"coeffs", "tmat", "qpanel", "repack", "hs_fp64", "slice", "hs_split", "graph"};
     bool ok = false;
     for (const char *k : known) ok = ok || std::strcmp(k, family) == 0;
     if (!ok) return fail(h, FLAPW_ERR_ARG, std::string("unknown kernel family ") + family);
@@ -564,14 +971,15 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
     if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
     ProblemDev pd{P, Q, (const double *)(base + od), (double2 *)H, (double2 *)S, L.kp2, ldh, n_g, (int)L.kp2};
     std::vector<int> npt{(int)(np / kTile)};
-    if (prec == FLAPW_PREC_FP64) return run_fp64(h, {pd}, npt, s);
-    const int sl = slices ? slices : default_slices(prec);
+    const int band = effective_band(h, prec, L.kp2);
+    if (prec == FLAPW_PREC_FP64) return run_fp64(h, {pd}, npt, band, s);
+    const int sl = effective_slices(h, prec, L.kp2, slices);
     e = h->digits.ensure((size_t)digit_area_bytes(L.kp2, np, sl));
     if (e != hipSuccess) return dev_fail(h, e, "allocating digit buffer");
     const DigitArea da = digit_area(h->digits.p, L.kp2, np, sl);
     if ((st = slice_problem(h, pd, np, sl, da, s)) != FLAPW_OK) return st;
     SplitProblemDev sp{da.L, da.RS, da.RH, da.eL, da.eRS, da.eRH, (double2 *)H, (double2 *)S, ldh, n_g, (int)L.kp2};
-    return run_split(h, {sp}, npt, sl, s);
+    return run_split(h, {sp}, npt, sl, band, s);
 }
 
 flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const int *n_g, const double *const *g,
@@ -580,116 +988,91 @@ flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const i
                                flapw_stream stream)
 {
     if (!h) return FLAPW_ERR_ARG;
-    if (n_k < 1) return fail(h, FLAPW_ERR_ARG, "n_k must be >= 1");
-    if (!k || !n_g || !g || !H || !S || !ldh) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
-    if (prec != FLAPW_PREC_FP64 && prec != FLAPW_PREC_SPLIT_BF16 && prec != FLAPW_PREC_SPLIT_I8)
-        return fail(h, FLAPW_ERR_ARG, "unknown precision");
-    if (slices < 0 || slices > FLAPW_SLICES_CAP) return fail(h, FLAPW_ERR_ARG, "slices out of range");
-    if (prec == FLAPW_PREC_SPLIT_I8 && slices != 0 && (slices < 3 || slices > 6))
-        return fail(h, FLAPW_ERR_UNSUPPORTED, "int8 split precision supports 3..6 digits");
-    if (prec == FLAPW_PREC_SPLIT_BF16) return fail(h, FLAPW_ERR_UNSUPPORTED, "bf16 split precision is not built");
-    for (int i = 0; i < n_k; ++i) {
-        if (n_g[i] < 1) return fail(h, FLAPW_ERR_ARG, "n_g must be >= 1");
-        if (!g[i] || !H[i] || !S[i]) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
-        if (ldh[i] < n_g[i]) return fail(h, FLAPW_ERR_ARG, "ldh < n_g");
-    }
-    if (!finite_all(k, 3 * (size_t)n_k)) return fail(h, FLAPW_ERR_ARG, "non-finite k");
-    flapw_status st = check_radial(h, rad);
+    flapw_status st = check_generate(h, n_k, k, n_g, g, at, rad, pot, H, S, ldh, prec, slices);
     if (st != FLAPW_OK) return st;
-    if ((st = check_atoms(h, at, rad, true)) != FLAPW_OK) return st;
-    if ((st = check_potential(h, pot, rad)) != FLAPW_OK) return st;
-    if (h->device < 0) return fail(h, FLAPW_ERR_DEVICE, "no HIP device");
     hipStream_t s = (hipStream_t)stream;
+    GenPlan p;
+    GenBuffers b{&h->tmat, &h->tables, &h->gaunt, &h->tiles, &h->work, &h->digits, &h->host_tables, &h->host_gaunt,
+                 &h->host_tiles};
+    st = prepare_generate(h, n_k, k, n_g, g, at, rad, pot, H, S, ldh, prec, slices, 0, b, p, s, false);
+    if (st != FLAPW_OK) return st;
+    return enqueue_generate(h, p, s);
+}
 
-    Layout L;
-    build_layout(at, rad, true, L);
-    const long long ldt = 2LL * L.nlmax;
-    hipError_t e = h->tmat.ensure((size_t)rad->n_types * ldt * ldt * sizeof(double2));
-    if (e != hipSuccess) return dev_fail(h, e, "allocating T");
-    if ((st = build_T_impl(h, rad, pot, (double2 *)h->tmat.p, ldt, s)) != FLAPW_OK) return st;
-
-    auto &hb = h->host_tables;
-    hb.clear();
-    const size_t oa = put(hb, L.atoms.data(), L.atoms.size());
-    const size_t ot = put(hb, L.types.data(), L.types.size());
-    const size_t od = put(hb, L.d.data(), L.d.size());
-    const size_t oty = put(hb, L.atom_type.data(), L.atom_type.size());
-    const size_t onl = put(hb, L.atom_nl2.data(), L.atom_nl2.size());
-    const size_t orow = put(hb, L.atom_row.data(), L.atom_row.size());
-    if ((st = upload(h, h->tables, hb, s)) != FLAPW_OK) return st;
-    unsigned char *base = (unsigned char *)h->tables.p;
-    const double pref = 4.0 * kPi / std::sqrt(at->omega);
-
-    // Memory batches of k-points.  FP64: the P and Q panels of every k-point of a batch stay
-    // resident for one grouped contraction launch.  Split precision: P and Q of one k-point at a
-    // time are cut into digits (the FP64 panels are reused), and the digits of every k-point of a
-    // batch stay resident for the grouped launch.
-    size_t free_b = 0, total_b = 0;
-    e = hipMemGetInfo(&free_b, &total_b);
-    if (e != hipSuccess) return dev_fail(h, e, "hipMemGetInfo");
-    double frac = 0.55;
-    if (const char *env = std::getenv("FLAPW_WORK_FRACTION")) frac = std::atof(env);
-    const bool split = prec != FLAPW_PREC_FP64;
-    const int sl = split ? (slices ? slices : default_slices(prec)) : 0;
-    long long np_max = 0;
-    for (int i = 0; i < n_k; ++i) np_max = std::max(np_max, round_up(n_g[i], kTile));
-    const size_t panel_one = (size_t)2 * L.kp2 * np_max * sizeof(double2);
-    size_t budget = (size_t)(frac * (double)total_b);
-    std::vector<size_t> need(n_k);
-    for (int i = 0; i < n_k; ++i) {
-        const long long np = round_up(n_g[i], kTile);
-        need[i] = split ? (size_t)digit_area_bytes(L.kp2, np, sl) : (size_t)2 * L.kp2 * np * sizeof(double2);
+flapw_status flapw_plan_create(flapw_handle h, int n_k, const double *k, const int *n_g, const double *const *g,
+                               const flapw_atoms *at, const flapw_radial *rad, const flapw_potential *pot,
+                               flapw_z *const *H, flapw_z *const *S, const long *ldh, flapw_prec prec, int slices,
+                               flapw_plan *plan)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    if (!plan) return fail(h, FLAPW_ERR_ARG, "plan is NULL");
+    *plan = nullptr;
+    flapw_status st = check_generate(h, n_k, k, n_g, g, at, rad, pot, H, S, ldh, prec, slices);
+    if (st != FLAPW_OK) return st;
+    hipError_t e = init_fp64_kernels();
+    if (e == hipSuccess && prec != FLAPW_PREC_FP64) e = init_split_kernels();
+    if (e != hipSuccess) return dev_fail(h, e, "kernel attributes");
+    flapw_plan_s *pl = new (std::nothrow) flapw_plan_s();
+    if (!pl) return fail(h, FLAPW_ERR_NOMEM, "plan allocation");
+    pl->h = h;
+    GenPlan p;
+    GenBuffers b{&pl->tmat, &pl->tables, &pl->gaunt, &pl->desc, &pl->work, &pl->digits, &pl->h_tables, &pl->h_gaunt,
+                 &pl->h_desc};
+    st = prepare_generate(h, n_k, k, n_g, g, at, rad, pot, H, S, ldh, prec, slices, 0, b, p, nullptr, true);
+    hipStream_t cs = nullptr;
+    if (st == FLAPW_OK) {
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess) st = dev_fail(h, e, "capture stream");
     }
-    if (split) {
-        e = h->work.ensure(panel_one);
-        if (e != hipSuccess) return dev_fail(h, e, "allocating work buffer");
-        budget = budget > panel_one ? budget - panel_one : 0;
-    }
-    int i0 = 0;
-    while (i0 < n_k) {
-        int i1 = i0;
-        size_t tot = 0;
-        while (i1 < n_k && (i1 == i0 || tot + need[i1] <= budget)) tot += need[i1++];
-        e = (split ? h->digits : h->work).ensure(tot);
-        if (e != hipSuccess) return dev_fail(h, e, split ? "allocating digit buffer" : "allocating work buffer");
-        std::vector<ProblemDev> probs;
-        std::vector<SplitProblemDev> sprobs;
-        std::vector<int> npt;
-        size_t off = 0;
-        for (int i = i0; i < i1; ++i) {
-            const long long np = round_up(n_g[i], kTile);
-            double2 *P = (double2 *)((unsigned char *)h->work.p + (split ? 0 : off));
-            double2 *Q = P + L.kp2 * np;
-            {
-                ProfScope prof(h, "coeffs", s);
-                e = launch_coeffs(k + 3 * i, n_g[i], (int)np, g[i], (const AtomDev *)(base + oa), at->n_atoms,
-                                  (const TypeDev *)(base + ot), rad->n_types, pref, P, P, L.kp2, 2 * L.k, L.kp2, s);
+    if (st == FLAPW_OK) {
+        const bool prof = h->profiling;
+        h->profiling = false;                      // no event nodes inside the graph
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) st = dev_fail(h, e, "begin capture");
+        if (st == FLAPW_OK) {
+            flapw_status se = enqueue_generate(h, p, cs);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(cs, &graph);
+            if (se != FLAPW_OK) st = se;
+            else if (e != hipSuccess) st = dev_fail(h, e, "end capture");
+            else {
+                e = hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) st = dev_fail(h, e, "graph instantiation");
             }
-            if (e != hipSuccess) return dev_fail(h, e, "coefficient kernel");
-            {
-                ProfScope prof(h, "qpanel", s);
-                e = launch_qpanel((const double2 *)h->tmat.p, ldt, ldt * ldt, (const int *)(base + oty),
-                                  (const int *)(base + onl), (const long long *)(base + orow), at->n_atoms, P, Q,
-                                  L.kp2, (int)np, s);
-            }
-            if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
-            const ProblemDev pd{P, Q, (const double *)(base + od), (double2 *)H[i], (double2 *)S[i], L.kp2,
-                                (long long)ldh[i], n_g[i], (int)L.kp2};
-            if (split) {
-                const DigitArea da = digit_area((unsigned char *)h->digits.p + off, L.kp2, np, sl);
-                if ((st = slice_problem(h, pd, np, sl, da, s)) != FLAPW_OK) return st;
-                sprobs.push_back(SplitProblemDev{da.L, da.RS, da.RH, da.eL, da.eRS, da.eRH, (double2 *)H[i],
-                                                 (double2 *)S[i], (long long)ldh[i], n_g[i], (int)L.kp2});
-            } else {
-                probs.push_back(pd);
-            }
-            off += need[i];
-            npt.push_back((int)(np / kTile));
+            if (graph) (void)hipGraphDestroy(graph);
         }
-        st = split ? run_split(h, sprobs, npt, sl, s) : run_fp64(h, probs, npt, s);
-        if (st != FLAPW_OK) return st;
-        i0 = i1;
+        h->profiling = prof;
     }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (st != FLAPW_OK) {
+        flapw_plan_destroy(pl);
+        return st;
+    }
+    *plan = pl;
+    return FLAPW_OK;
+}
+
+flapw_status flapw_plan_launch(flapw_plan plan, flapw_stream stream)
+{
+    if (!plan || !plan->exec) return FLAPW_ERR_ARG;
+    ProfScope prof(plan->h, "graph", (hipStream_t)stream);
+    hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(plan->h, e, "graph launch");
+    return FLAPW_OK;
+}
+
+flapw_status flapw_plan_destroy(flapw_plan plan)
+{
+    if (!plan) return FLAPW_ERR_ARG;
+    (void)hipDeviceSynchronize();
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    plan->work.release();
+    plan->digits.release();
+    plan->tmat.release();
+    plan->tables.release();
+    plan->gaunt.release();
+    plan->desc.release();
+    delete plan;
     return FLAPW_OK;
 }
 

@@ -96,6 +96,9 @@ hipError_t launch_repack(const double2 *A, const double2 *B, long long lda, int 
                          hipStream_t s);
 
 long long split_digit_bytes(long long kp2, long long np, int s);
+// dynamic-LDS attributes of the contraction kernels (set once, before any launch or graph capture)
+hipError_t init_fp64_kernels();
+hipError_t init_split_kernels();
 hipError_t launch_split_slice(const double2 *P, const double2 *Q, const double *d, long long ld, int kp2, int np,
                               int slices, int *eL, int *eRS, int *eRH, int8_t *L, int8_t *RS, int8_t *RH,
                               hipStream_t s);

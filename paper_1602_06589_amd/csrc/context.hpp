@@ -61,10 +61,26 @@ struct flapw_context {
     flapw::DevBuf sdesc;       // split precision: descriptors
     std::vector<unsigned char> host_tables, host_gaunt, host_tiles, host_sdesc;
     std::vector<long long> host_src;
+    // tuning (flapw_tune): chosen digit count and tile band per (precision, padded contraction rows)
+    struct Tuned {
+        int prec;
+        long long kp2;
+        int slices;
+        int band;
+    };
+    std::vector<Tuned> tuned;
     // profiling: event pairs per kernel family, recorded while `profiling` is set
     bool profiling = false;
     std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> prof;
     std::vector<hipEvent_t> spare_events;
+};
+
+// A captured S/H generation (flapw_plan_create): its own device buffers and the graph.
+struct flapw_plan_s {
+    flapw_handle h = nullptr;
+    flapw::DevBuf work, digits, tmat, tables, gaunt, desc;
+    std::vector<unsigned char> h_tables, h_gaunt, h_desc;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace flapw {

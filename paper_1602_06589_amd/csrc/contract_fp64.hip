@@ -308,15 +308,23 @@ __global__ void repack_kernel(const double2 *__restrict__ A, const double2 *__re
 
 }  // namespace
 
+hipError_t init_fp64_kernels()
+{
+    static hipError_t done = hipErrorNotReady;
+    if (done == hipSuccess) return done;
+    hipError_t e = hipFuncSetAttribute((const void *)hs_fp64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)sizeof(HsSmem));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)qpanel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sizeof(QSmem));
+    done = e;
+    return e;
+}
+
 hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_tiles, hipStream_t s)
 {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)hs_fp64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)sizeof(HsSmem));
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    hipError_t e = init_fp64_kernels();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(hs_fp64_kernel, dim3(n_tiles), dim3(kHsThreads), sizeof(HsSmem), s, probs, tiles);
     return hipGetLastError();
 }
@@ -325,13 +333,8 @@ hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, con
                          const long long *atom_row, int n_atoms, const double2 *P, double2 *Q, long long ldp, int np,
                          hipStream_t s)
 {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)qpanel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)sizeof(QSmem));
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    hipError_t e = init_fp64_kernels();
+    if (e != hipSuccess) return e;
     // row tiles: enough for the largest atom block (2 NL <= ldt)
     const int row_tiles = (int)((ldt + kTile - 1) / kTile);
     hipLaunchKernelGGL(qpanel_kernel, dim3(np / kTile, n_atoms, row_tiles), dim3(kThreads), sizeof(QSmem), s, T, ldt,

@@ -322,17 +322,19 @@ __global__ __launch_bounds__(256, 1) void hs_split_i8_kernel(const SplitProblemD
 }
 
 template <int S>
+hipError_t init_split_s()
+{
+    return hipFuncSetAttribute((const void *)hs_split_i8_kernel<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               SplitSmem<S>::kBytes);
+}
+
+template <int S>
 hipError_t launch_split_s(const SplitProblemDev *probs, const TileDev *tiles, int n_tiles, hipStream_t s)
 {
     constexpr int smem = SplitSmem<S>::kBytes;
     static_assert(smem <= 163840, "LDS budget");
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)hs_split_i8_kernel<S>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, smem);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    hipError_t e = init_split_kernels();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(hs_split_i8_kernel<S>, dim3(n_tiles), dim3(256), smem, s, probs, tiles);
     return hipGetLastError();
 }
@@ -354,6 +356,18 @@ hipError_t launch_digits_s(const double2 *P, const double2 *Q, const double *d, 
 }  // namespace
 
 long long split_digit_bytes(long long kp2, long long np, int s) { return 3LL * 2 * s * kp2 * np; }
+
+hipError_t init_split_kernels()
+{
+    static hipError_t done = hipErrorNotReady;
+    if (done == hipSuccess) return done;
+    hipError_t e = init_split_s<3>();
+    if (e == hipSuccess) e = init_split_s<4>();
+    if (e == hipSuccess) e = init_split_s<5>();
+    if (e == hipSuccess) e = init_split_s<6>();
+    done = e;
+    return e;
+}
 
 hipError_t launch_split_slice(const double2 *P, const double2 *Q, const double *d, long long ld, int kp2, int np,
                               int slices, int *eL, int *eRS, int *eRH, int8_t *L, int8_t *RS, int8_t *RH,

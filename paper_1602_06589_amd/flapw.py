@@ -33,8 +33,8 @@ _STATUS = {0: "FLAPW_OK", -1: "FLAPW_ERR_ARG", -2: "FLAPW_ERR_WRONSKIAN", -3: "F
            -4: "FLAPW_ERR_NOMEM", -5: "FLAPW_ERR_DEVICE", -6: "FLAPW_ERR_UNSUPPORTED"}
 
 EXPORTS = ["flapw_create", "flapw_destroy", "flapw_status_string", "flapw_last_error", "flapw_workspace_bytes",
-           "flapw_coeffs", "flapw_build_T", "flapw_hs_contract", "flapw_hs_generate", "flapw_profile_enable",
-           "flapw_profile_query"]
+           "flapw_coeffs", "flapw_build_T", "flapw_hs_contract", "flapw_hs_generate", "flapw_plan_create",
+           "flapw_plan_launch", "flapw_plan_destroy", "flapw_tune", "flapw_profile_enable", "flapw_profile_query"]
 
 
 class FlapwError(RuntimeError):
@@ -82,6 +82,11 @@ def load_library(path: str = LIB_PATH):
         lib.flapw_build_T.argtypes = [P, P, P, P, L, P]
         lib.flapw_hs_contract.argtypes = [P, I, P, P, P, P, L, P, L, P, P, L, I, I, P]
         lib.flapw_hs_generate.argtypes = [P, I, P, P, P, P, P, P, P, P, P, I, I, P]
+        lib.flapw_plan_create.argtypes = [P, I, P, P, P, P, P, P, P, P, P, I, I, ctypes.POINTER(P)]
+        lib.flapw_plan_launch.argtypes = [P, P]
+        lib.flapw_plan_destroy.argtypes = [P]
+        D = ctypes.POINTER(ctypes.c_double)
+        lib.flapw_tune.argtypes = [P, P, I, P, P, P, P, I, ctypes.c_double, ctypes.POINTER(I), ctypes.POINTER(I), D, D]
         lib.flapw_profile_enable.argtypes = [P, I]
         lib.flapw_profile_query.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_double)]
         for f in EXPORTS:
@@ -231,9 +236,7 @@ class Flapw:
                                                 _stream(stream)))
         return H, S
 
-    def hs_generate(self, system, kpts, gvecs: Sequence, prec="fp64", slices: int = 0, out: Optional[List] = None,
-                    stream=None):
-        """H and S of every k-point.  gvecs: device tensors (n_g_i, 3).  Returns [(H_i, S_i)]."""
+    def _generate_args(self, system, kpts, gvecs, out):
         import torch
         self._keep = []
         nk = len(gvecs)
@@ -247,7 +250,72 @@ class Flapw:
         sp = (ctypes.c_void_p * nk)(*[_dptr(s) for _, s in out])
         ld = np.array([int(h.shape[1]) for h, _ in out], dtype=np.int64)
         rad, at, pot = self._radial(system), self._atoms(system), self._potential(system)
-        self._check(self._lib.flapw_hs_generate(self._h, nk, _ptr(kk), _ptr(ng), gp, ctypes.byref(at),
-                                                ctypes.byref(rad), ctypes.byref(pot), hp, sp, _ptr(ld),
-                                                PRECISIONS.get(prec, prec), int(slices), _stream(stream)))
+        self._keep += [kk, ng, gp, hp, sp, ld, rad, at, pot]
+        return out, (nk, _ptr(kk), _ptr(ng), gp, ctypes.byref(at), ctypes.byref(rad), ctypes.byref(pot), hp, sp,
+                     _ptr(ld))
+
+    def hs_generate(self, system, kpts, gvecs: Sequence, prec="fp64", slices: int = 0, out: Optional[List] = None,
+                    stream=None):
+        """H and S of every k-point.  gvecs: device tensors (n_g_i, 3).  Returns [(H_i, S_i)]."""
+        out, args = self._generate_args(system, kpts, gvecs, out)
+        self._check(self._lib.flapw_hs_generate(self._h, *args, PRECISIONS.get(prec, prec), int(slices),
+                                                _stream(stream)))
         return out
+
+    def plan(self, system, kpts, gvecs: Sequence, prec="fp64", slices: int = 0, out: Optional[List] = None):
+        """Captures the generation of hs_generate into a HIP graph; returns a Plan whose launch()
+        replays it into the same outputs (Plan.out)."""
+        out, args = self._generate_args(system, kpts, gvecs, out)
+        handle = ctypes.c_void_p()
+        self._check(self._lib.flapw_plan_create(self._h, *args, PRECISIONS.get(prec, prec), int(slices),
+                                                ctypes.byref(handle)))
+        return Plan(self, handle, out, list(gvecs))
+
+    def tune(self, system, k, g, prec="i8", tol: float = 1e-10):
+        """Runs the autotuner on one k-point (g: device tensor (n_g, 3)); the handle keeps the choice.
+        Returns {"slices", "band", "digit_err" (3..6 digits), "band_ms" (bands 1, 2, 4, 8, 16)}."""
+        self._keep = []
+        kk = _f64(k)
+        rad, at, pot = self._radial(system), self._atoms(system), self._potential(system)
+        sl, band = ctypes.c_int(), ctypes.c_int()
+        err = (ctypes.c_double * 4)()
+        ms = (ctypes.c_double * 5)()
+        st = self._lib.flapw_tune(self._h, _ptr(kk), int(g.shape[0]), _dptr(g), ctypes.byref(at), ctypes.byref(rad),
+                                  ctypes.byref(pot), PRECISIONS.get(prec, prec), float(tol), ctypes.byref(sl),
+                                  ctypes.byref(band), err, ms)
+        res = {"slices": sl.value, "band": band.value, "digit_err": list(err), "band_ms": list(ms)}
+        if st != 0:
+            e = FlapwError(st, self._lib.flapw_last_error(self._h).decode())
+            e.result = res
+            raise e
+        return res
+
+
+class Plan:
+    """A captured H/S generation (see Flapw.plan).  Keeps its outputs and G lists alive."""
+
+    def __init__(self, owner: "Flapw", handle, out, gvecs):
+        self._owner, self._p, self.out, self._g = owner, handle, out, gvecs
+
+    def launch(self, stream=None):
+        if not self._p:
+            raise FlapwError(-1, "plan destroyed")
+        self._owner._check(self._owner._lib.flapw_plan_launch(self._p, _stream(stream)))
+        return self.out
+
+    def close(self):
+        if self._p:
+            self._owner._lib.flapw_plan_destroy(self._p)
+            self._p = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -133,3 +133,66 @@ def test_validation_lpot(handle):
     cell = synthcells.config(0)
     cell.lpot = 13
     assert _call_build_T(handle, cell) == -1
+
+
+def _gen_args(f, cell, n_g=None):
+    """Argument tuple of flapw_hs_generate / flapw_plan_create up to (but excluding) prec, with
+    stand-in device pointers (the calls must fail before touching them)."""
+    from paper_1602_06589_amd import flapw as F
+    f._keep = []
+    n = np.array([cell.n_g(0) if n_g is None else n_g], np.int32)
+    k = np.zeros(3)
+    ptrs = [(ctypes.c_void_p * 1)(0x1000 * (i + 1)) for i in range(3)]
+    ld = np.array([max(int(n[0]), 1)], np.int64)
+    rad, at, pot = f._radial(cell), f._atoms(cell), f._potential(cell)
+    f._keep += [n, k, ptrs, ld, rad, at, pot]
+    return (f._h, 1, F._ptr(k), F._ptr(n), ptrs[0], ctypes.byref(at), ctypes.byref(rad), ctypes.byref(pot), ptrs[1],
+            ptrs[2], F._ptr(ld))
+
+
+def test_plan_validation(handle):
+    cell = synthcells.config(0)
+    out = ctypes.c_void_p(0x1234)
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell, n_g=0), 0, 0, ctypes.byref(out)) == -1
+    assert out.value is None                                          # cleared on failure
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 1, 0, ctypes.byref(out)) == -6
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 2, 7, ctypes.byref(out)) == -6
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 0, 0, None) == -1
+    assert handle._lib.flapw_plan_launch(None, None) == -1
+    assert handle._lib.flapw_plan_destroy(None) == -1
+
+
+def _call_tune(f, cell, tol, prec=2, n_g=None):
+    from paper_1602_06589_amd import flapw as F
+    f._keep = []
+    rad, at, pot = f._radial(cell), f._atoms(cell), f._potential(cell)
+    k = np.zeros(3)
+    sl, band = ctypes.c_int(-1), ctypes.c_int(-1)
+    err = (ctypes.c_double * 4)()
+    st = f._lib.flapw_tune(f._h, F._ptr(k), cell.n_g(0) if n_g is None else n_g, ctypes.c_void_p(0x1000),
+                           ctypes.byref(at), ctypes.byref(rad), ctypes.byref(pot), prec, tol, ctypes.byref(sl),
+                           ctypes.byref(band), err, None)
+    return st, sl.value, band.value
+
+
+def test_tune_validation(handle):
+    cell = synthcells.config(0)
+    assert _call_tune(handle, cell, 0.0)[0] == -1
+    assert _call_tune(handle, cell, float("nan"))[0] == -1
+    assert _call_tune(handle, cell, 1e-10, n_g=0)[0] == -1
+    assert _call_tune(handle, cell, 1e-10, prec=1)[0] == -6
+    assert _call_tune(handle, cell, 1e-10, prec=5)[0] == -1
+    bad = synthcells.config(0)
+    bad.i_uu[0, 2, 3, 5] += 1e-3
+    assert _call_tune(handle, bad, 1e-10)[0] == -3
+
+
+def test_plan_and_tune_no_device(handle):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    cell = synthcells.config(0)
+    out = ctypes.c_void_p()
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 2, 0, ctypes.byref(out)) == -5
+    st, sl, band = _call_tune(handle, cell, 1e-10)
+    assert st == -5 and sl == -1 and band == -1                       # outputs untouched on failure
