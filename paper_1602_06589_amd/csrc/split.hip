@@ -162,14 +162,13 @@ __global__ __launch_bounds__(256) void digits_kernel(const double2 *__restrict__
 
 // ----------------------------------------------------------------------------- contraction
 
-// Negate the 16 signed bytes of a fragment (no byte is -128): -x = ((x ^ 0x7f) + 1) ^ 0x80 per
-// byte; x ^ 0x7f <= 0xfe for every byte, so the +1 never carries into the next byte.
-__device__ __forceinline__ v4i neg_i8x16(v4i x)
+// Negation of the imaginary half of an A fragment (lanes 32-63), per signed byte with no byte
+// equal to -128: -x = ((x ^ 0x7f) + 1) ^ 0x80.  x ^ 0x7f <= 0xfe, so the +1 never carries into
+// the next byte.  With the three constants masked to zero on lanes 0-31 the same three
+// instructions leave those lanes unchanged.
+__device__ __forceinline__ int neg_lanes(int x, unsigned m7f, unsigned m01, unsigned m80)
 {
-    v4i r;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) r[i] = (int)((((unsigned)x[i] ^ 0x7f7f7f7fu) + 0x01010101u) ^ 0x80808080u);
-    return r;
+    return (int)((((unsigned)x ^ m7f) + m01) ^ m80);
 }
 
 template <int S>
@@ -189,8 +188,8 @@ __global__ __launch_bounds__(256, 1) void hs_split_i8_kernel(const SplitProblemD
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     using SM = SplitSmem<S>;
-    constexpr int kRunUnits = SM::kRunBytes / 16;                 // 16-byte units of one run (128 S)
-    constexpr int kPerRun = (kRunUnits + 255) / 256;              // units per thread and run
+    constexpr int kRunSegs = SM::kRunBytes / 1024;                // 1 KB segments of one run (2 S)
+    constexpr int kSegsPerWave = kRunSegs;                        // a stage is 4 runs, spread over 4 waves
 
     const TileDev td = tiles[blockIdx.x];
     const SplitProblemDev pb = probs[td.prob];
@@ -219,93 +218,84 @@ __global__ __launch_bounds__(256, 1) void hs_split_i8_kernel(const SplitProblemD
 #pragma unroll
     for (int r = 0; r < 32; ++r) facc[r * 64] = 0.0;
 
-    v4i pre[4][kPerRun];
-#define SPLIT_LOAD(st)                                                                          \
+    // Stages are copied global -> LDS by the load unit itself (global_load_lds_dwordx4): one
+    // instruction moves a contiguous 1 KB segment, lane l's 16 bytes landing at +16 l.  No
+    // registers hold staged data; the copies of stage st + 1 are issued at the start of stage st
+    // and complete by the barrier that ends it (the barrier waits for all outstanding loads).
+#define SPLIT_COPY(st, b)                                                                       \
     do {                                                                                        \
-        _Pragma("unroll") for (int run = 0; run < 4; ++run)                                     \
-            _Pragma("unroll") for (int j = 0; j < kPerRun; ++j) {                               \
-                const int u_ = tid + 256 * j;                                                   \
-                if (u_ < kRunUnits)                                                             \
-                    pre[run][j] = *((gv4i *)(run_base[run] + (long long)(st) * stage_step) + u_); \
-            }                                                                                   \
-    } while (0)
-#define SPLIT_STORE(b)                                                                          \
-    do {                                                                                        \
-        unsigned char *dst_ = smem_raw + (b) * SM::kStageBytes;                                 \
-        _Pragma("unroll") for (int run = 0; run < 4; ++run)                                     \
-            _Pragma("unroll") for (int j = 0; j < kPerRun; ++j) {                               \
-                const int u_ = tid + 256 * j;                                                   \
-                if (u_ < kRunUnits) *reinterpret_cast<v4i *>(dst_ + run * SM::kRunBytes + 16 * u_) = pre[run][j]; \
-            }                                                                                   \
+        _Pragma("unroll") for (int j = 0; j < kSegsPerWave; ++j) {                              \
+            const int sg_ = wave + 4 * j, run_ = sg_ / kRunSegs, off_ = (sg_ % kRunSegs) * 1024; \
+            const int8_t *src_ = run_base[run_] + (long long)(st) * stage_step + off_ + lane * 16; \
+            __builtin_amdgcn_global_load_lds((const int __attribute__((address_space(1))) *)src_, \
+                (int __attribute__((address_space(3))) *)(smem_raw + (b) * SM::kStageBytes + sg_ * 1024), 16, 0, 0); \
+        }                                                                                       \
     } while (0)
 
-    SPLIT_LOAD(0);
-    SPLIT_STORE(0);
+    SPLIT_COPY(0, 0);
     __syncthreads();
 
     const int half_a = lane >> 5, col = lane & 31;
-    const unsigned negmask = half_a ? 0xffffffffu : 0u;          // lanes 32-63 carry Xi
-    for (int st = 0; st < nst; ++st) {
-        const int b = st & 1;
-        if (st + 1 < nst) SPLIT_LOAD(st + 1);
-        const unsigned char *stage = smem_raw + b * SM::kStageBytes;
+    // lanes 32-63 carry Xi and negate it for the Im products
+    const unsigned m7f = half_a ? 0x7f7f7f7fu : 0u, m01 = half_a ? 0x01010101u : 0u, m80 = half_a ? 0x80808080u : 0u;
+    // Outer loop over flush periods, inner loop over stages: the int32 accumulators stay in the
+    // matrix-core registers for a whole period and are read only by the flush.
+    for (int st0 = 0; st0 < nst; st0 += kFlushStages) {
+        const int st1 = min(nst, st0 + kFlushStages);
+        for (int st = st0; st < st1; ++st) {
+            const int b = st & 1;
+            if (st + 1 < nst) SPLIT_COPY(st + 1, b ^ 1);
+            const unsigned char *stage = smem_raw + b * SM::kStageBytes;
 #pragma unroll 1
-        for (int kk = 0; kk < kChunksPerStage; ++kk) {
-            const unsigned char *lrun = stage + wmb * SM::kRunBytes + kk * S * 1024 + half_a * 512 + col * 16;
-            const unsigned char *rrun = stage + (2 + wnb) * SM::kRunBytes + kk * S * 1024 + col * 16;
-            // all A reads and the first B pair issued back to back; the negation of the
-            // imaginary half (lanes 32-63) is a lane select, not a branch
-            v4i a_re[S], a_im[S];
+            for (int kk = 0; kk < kChunksPerStage; ++kk) {
+                const unsigned char *lrun = stage + wmb * SM::kRunBytes + kk * S * 1024 + half_a * 512 + col * 16;
+                const unsigned char *rrun = stage + (2 + wnb) * SM::kRunBytes + kk * S * 1024 + col * 16;
+                // all A reads and the first B pair issued back to back
+                v4i a_re[S], a_im[S];
 #pragma unroll
-            for (int p = 0; p < S; ++p) a_re[p] = *reinterpret_cast<const v4i *>(lrun + p * 1024);
-            v4i b_re = *reinterpret_cast<const v4i *>(rrun + half_a * 512);
-            v4i b_im = *reinterpret_cast<const v4i *>(rrun + (1 - half_a) * 512);
+                for (int p = 0; p < S; ++p) a_re[p] = *reinterpret_cast<const v4i *>(lrun + p * 1024);
+                v4i b_re = *reinterpret_cast<const v4i *>(rrun + half_a * 512);
+                v4i b_im = *reinterpret_cast<const v4i *>(rrun + (1 - half_a) * 512);
 #pragma unroll
-            for (int p = 0; p < S; ++p) {
-                const v4i n = neg_i8x16(a_re[p]);
+                for (int p = 0; p < S; ++p)
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    a_im[p][i] = (int)(((unsigned)n[i] & negmask) | ((unsigned)a_re[p][i] & ~negmask));
-            }
+                    for (int i = 0; i < 4; ++i) a_im[p][i] = neg_lanes(a_re[p][i], m7f, m01, m80);
 #pragma unroll
-            for (int q = 0; q < S; ++q) {
-                v4i nb_re = b_re, nb_im = b_im;
-                if (q + 1 < S) {                 // B fragments of the next q, read ahead
-                    nb_re = *reinterpret_cast<const v4i *>(rrun + (q + 1) * 1024 + half_a * 512);
-                    nb_im = *reinterpret_cast<const v4i *>(rrun + (q + 1) * 1024 + (1 - half_a) * 512);
+                for (int q = 0; q < S; ++q) {
+                    v4i nb_re = b_re, nb_im = b_im;
+                    if (q + 1 < S) {                 // B fragments of the next q, read ahead
+                        nb_re = *reinterpret_cast<const v4i *>(rrun + (q + 1) * 1024 + half_a * 512);
+                        nb_im = *reinterpret_cast<const v4i *>(rrun + (q + 1) * 1024 + (1 - half_a) * 512);
+                    }
+                    // Re products first: they do not wait for the negated fragments
+#pragma unroll
+                    for (int p = 0; p + q < S; ++p)
+                        acc_re[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_re[p], b_re, acc_re[p + q], 0, 0, 0);
+#pragma unroll
+                    for (int p = 0; p + q < S; ++p)
+                        acc_im[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_im[p], b_im, acc_im[p + q], 0, 0, 0);
+                    b_re = nb_re;
+                    b_im = nb_im;
                 }
-                // Re products first: they do not wait for the negated fragments
-#pragma unroll
-                for (int p = 0; p + q < S; ++p)
-                    acc_re[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_re[p], b_re, acc_re[p + q], 0, 0, 0);
-#pragma unroll
-                for (int p = 0; p + q < S; ++p)
-                    acc_im[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_im[p], b_im, acc_im[p + q], 0, 0, 0);
-                b_re = nb_re;
-                b_im = nb_im;
             }
+            __syncthreads();
         }
-        if (st + 1 < nst) SPLIT_STORE(b ^ 1);
-        if ((st + 1) % kFlushStages == 0 || st + 1 == nst) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                double sr = 0.0, si = 0.0;
+        for (int r = 0; r < 16; ++r) {
+            double sr = 0.0, si = 0.0;
 #pragma unroll
-                for (int g = 0; g < S; ++g) {
-                    const double w = ldexp(1.0, -7 * (g + 2));
-                    sr += w * (double)acc_re[g][r];
-                    si += w * (double)acc_im[g][r];
-                    acc_re[g][r] = 0;
-                    acc_im[g][r] = 0;
-                }
-                facc[r * 64] += sr;
-                facc[(16 + r) * 64] += si;
+            for (int g = 0; g < S; ++g) {
+                const double w = ldexp(1.0, -7 * (g + 2));
+                sr += w * (double)acc_re[g][r];
+                si += w * (double)acc_im[g][r];
+                acc_re[g][r] = 0;
+                acc_im[g][r] = 0;
             }
+            facc[r * 64] += sr;
+            facc[(16 + r) * 64] += si;
         }
-        __syncthreads();
     }
-#undef SPLIT_LOAD
-#undef SPLIT_STORE
+#undef SPLIT_COPY
 
     // epilogue: scale by 2^(eL_row + eR_col); upper triangle; diagonal imaginary part zero
     const long long i0 = (long long)td.ti * 64 + wmb * 32, j0 = (long long)td.tj * 64 + wnb * 32;
