@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--precs", default="i8,fp64",
                     help="paths to measure; the first is the headline (value, roofline)")
     ap.add_argument("--slices", type=int, default=0)
+    ap.add_argument("--s-method", default="gemm", choices=["gemm", "legendre"],
+                    help="S with H on the matrix cores (the paper's method) or through the addition theorem")
     ap.add_argument("--nk", type=int, default=0, help="use only the first nk k-points (0 = all)")
     ap.add_argument("--cpu-sample", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -142,7 +144,10 @@ def main():
     gdev = [torch.as_tensor(np.ascontiguousarray(g), device="cuda") for g in cell.gvecs]
     f_alg = [cell.flops_per_k(i) for i in range(nk)]
     kr = cell.k_rows()
-    f_contract = [16.0 * kr * cell.n_g(i) * (cell.n_g(i) + 1.0) for i in range(nk)]
+    # algorithmic flops of the contraction kernel: S and H triangles, or H alone when S comes from
+    # the addition theorem
+    per_mat = [8.0 * kr * cell.n_g(i) * (cell.n_g(i) + 1.0) for i in range(nk)]
+    f_contract = [(2.0 if args.s_method == "gemm" else 1.0) * x for x in per_mat]
     precs = [p.strip() for p in args.precs.split(",") if p.strip()]
     stream = torch.cuda.current_stream()
     print(f"# workload {cell.name}: {cell.n_atoms} atoms, {cell.n_types} types, K={kr}, {nk} k-points, "
@@ -152,6 +157,7 @@ def main():
     results, outs = {}, {}
     for prec in precs:
         with Flapw() as fl:                   # one handle per path: its work buffers are freed after
+            fl.set_s_method(args.s_method)
             out = [(torch.zeros((cell.n_g(i), cell.n_g(i)), dtype=torch.complex128, device="cuda"),
                     torch.zeros((cell.n_g(i), cell.n_g(i)), dtype=torch.complex128, device="cuda")) for i in range(nk)]
             for _ in range(args.warmup):
@@ -168,7 +174,8 @@ def main():
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
             ms = e0.elapsed_time(e1) / args.steps
-            kern = {fam: fl.kernel_time(fam) for fam in ("coeffs", "tmat", "qpanel", "hs_fp64", "slice", "hs_split")}
+            kern = {fam: fl.kernel_time(fam)
+                    for fam in ("coeffs", "tmat", "qpanel", "hs_fp64", "slice", "hs_split", "leg_prep", "s_legendre")}
             fl.profile(False)
             n_l, k_ms = kern[KERNEL[prec]]
             achieved = sum(f_contract) * args.steps / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
@@ -202,7 +209,9 @@ def main():
             "frac": (achieved / PEAKS[head]) if achieved else None, "traffic": traffic,
             "avg_launch_ms": k_ms, "launches_per_step": n_launch,
             "flops_per_launch": sum(f_contract) / n_launch,
-            "algorithmic_unit": "FP64-equivalent flops of the S and H upper triangles (8 K N(N+1) each)"}
+            "algorithmic_unit": ("FP64-equivalent flops of the S and H upper triangles (8 K N(N+1) each)"
+                                 if args.s_method == "gemm" else
+                                 "FP64-equivalent flops of the H upper triangle (8 K N(N+1)); S by the addition theorem")}
     if head != "fp64" and achieved:
         ex = achieved * executed_per_flop(slices)
         roof.update({"executed_ops_per_flop": executed_per_flop(slices), "executed_achieved": ex,
@@ -215,7 +224,8 @@ def main():
         "speedup_vs_fp64": (results["fp64"]["ms_per_step"] / r["ms_per_step"]) if "fp64" in results and head != "fp64" else None,
         "config": {"workload": cell.name, "n_atoms": cell.n_atoms, "n_types": cell.n_types, "K": kr,
                    "lmax": int(cell.lmax.max()), "lpot": cell.lpot, "n_kpoints": nk,
-                   "n_g": [cell.n_g(i) for i in range(nk)], "path": head, "slices": args.slices},
+                   "n_g": [cell.n_g(i) for i in range(nk)], "path": head, "slices": args.slices,
+                   "s_method": args.s_method},
         "ms_per_kpoint": r["ms_per_kpoint"],
         "roofline": roof,
         "cpu_baseline": base,

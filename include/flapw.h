@@ -168,6 +168,27 @@ flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const i
                                flapw_z *const *H, flapw_z *const *S, const long *ldh, flapw_prec prec, int slices,
                                flapw_stream stream);
 
+/* Method for S in flapw_hs_generate / flapw_plan_create (a handle setting, FLAPW_S_GEMM by
+ * default).
+ *   FLAPW_S_GEMM     : S = P^H D P on the matrix cores with H (eq. def_overlap; in the chosen
+ *                      precision: FP64 or split digits).
+ *   FLAPW_S_LEGENDRE : S through the addition theorem (section 3.1, eq. overlap_no_m with the
+ *                      prefactor 4 pi / Omega): the sum over m becomes (2l+1)/(4 pi) P_l of the
+ *                      angle between K_t and K_t', and the sum over atoms becomes, per atom type,
+ *                      E^H E with E the plane-wave phases of that type's atoms.  Always FP64
+ *                      (any prec); the contraction then computes H alone.  Same S up to rounding.
+ * Plans use the method set when they are created. */
+typedef enum { FLAPW_S_GEMM = 0, FLAPW_S_LEGENDRE = 1 } flapw_s_method;
+flapw_status flapw_set_s_method(flapw_handle h, flapw_s_method method);
+
+/* S of one k-point through the addition theorem (FLAPW_S_LEGENDRE above), FP64.
+ *   k[3] host, g device [n_g][3] Cartesian G (K_t = k + G_t), at/rad as flapw_coeffs (positions
+ *   required, omega > 0).  S device, column-major, lds >= n_g; written on the upper triangle with
+ *   the diagonal imaginary part exactly 0; the strictly lower part is untouched.
+ * Errors: FLAPW_ERR_ARG, FLAPW_ERR_WRONSKIAN, FLAPW_ERR_DEVICE (as flapw_coeffs). */
+flapw_status flapw_s_legendre(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
+                              const flapw_radial *rad, flapw_z *S, long lds, flapw_stream stream);
+
 /* Captured generation.  flapw_plan_create validates like flapw_hs_generate, allocates device
  * buffers owned by the plan (not shared with the handle), uploads every descriptor, and records
  * the whole generation (T, and per k-point coefficients, panels, digit slicing, then the grouped
@@ -209,7 +230,8 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
  * HIP events on the launch stream around every launch of its kernels.  flapw_profile_query
  * waits for the recorded events of one kernel family and returns the number of launches and
  * their summed duration in milliseconds since the last flapw_profile_enable(h, 1).
- * Families: "coeffs", "tmat", "qpanel", "repack", "hs_fp64", "slice", "hs_split", "graph"
+ * Families: "coeffs", "tmat", "qpanel", "repack", "hs_fp64", "slice", "hs_split", "leg_prep",
+ * "s_legendre", "graph"
  * (a whole flapw_plan_launch; kernels inside a graph are not timed one by one).
  * Errors: FLAPW_ERR_ARG for an unknown family or NULL output pointer. */
 flapw_status flapw_profile_enable(flapw_handle h, int on);

@@ -124,6 +124,12 @@ struct Layout {
     long long k = 0;                        // sum_a NL_a
     long long kp2 = 0;                      // padded 2K
     int nlmax = 0;
+    // S through the addition theorem: atom positions, the row of each atom in the phase panel
+    // (atoms grouped by type, each group padded to 16 rows), and the per-type row ranges
+    std::vector<double> apos;
+    std::vector<int> leg_row;
+    std::vector<LegTypeRange> leg_ranges;
+    long long ldE = 0;
 };
 
 void build_layout(const flapw_atoms *at, const flapw_radial *rad, bool work_layout, Layout &L)
@@ -148,6 +154,7 @@ void build_layout(const flapw_atoms *at, const flapw_radial *rad, bool work_layo
             r.ud = rad->ud[q];
             r.dud = rad->dud[q];
             r.inv_w = 1.0 / (rad->ud[q] * rad->du[q] - rad->u[q] * rad->dud[q]);
+            r.ud_norm2 = rad->ud_norm2[q];
         }
     }
     L.nlmax = (lm + 1) * (lm + 1);
@@ -174,6 +181,23 @@ void build_layout(const flapw_atoms *at, const flapw_radial *rad, bool work_layo
     }
     L.k = off;
     L.kp2 = round_up(2 * off, kRowAlign);
+    L.apos.resize(3 * (size_t)na);
+    for (int a = 0; a < na; ++a)
+        for (int i = 0; i < 3; ++i) L.apos[3 * a + i] = L.atoms[a].pos[i];
+    L.leg_row.assign(na, 0);
+    L.leg_ranges.assign(rad->n_types, LegTypeRange{0, 0, 0, 0});
+    {
+        int row = 0;
+        for (int t = 0; t < rad->n_types; ++t) {
+            int cnt = 0;
+            for (int a = 0; a < na; ++a)
+                if (at->type[a] == t) L.leg_row[a] = row + cnt++;
+            const int rows = (int)round_up(cnt, kKTile);
+            L.leg_ranges[t] = LegTypeRange{row, rows, rad->lmax[t], 0};
+            row += rows;
+        }
+        L.ldE = std::max(row, kKTile);
+    }
     L.d.assign(L.kp2, 0.0);
     for (int a = 0; a < na; ++a) {
         const int t = at->type[a], lmx = rad->lmax[t];
@@ -285,7 +309,10 @@ flapw_status build_T_impl(flapw_handle h, const flapw_radial *rad, const flapw_p
 // work-groups running together share operand panels) and remapped so that each of the eight
 // XCDs (work-group b runs on XCD b % 8) receives a contiguous run of that order.  With mats = 2
 // (split precision) every (ti, tj) gives an S tile and an H tile next to each other.
-void build_tiles(const std::vector<int> &np_tiles, int mats, std::vector<TileDev> &out, int kBand = 4)
+// Tiles (prob, ti <= tj, m) for m in [m0, m1) (split precision: 0 = S, 1 = H), in bands of kBand
+// tile rows, then dealt round-robin over the 8 XCDs so that neighbours in the band order run on
+// the same XCD (and share its L2).
+void build_tiles(const std::vector<int> &np_tiles, int m0, int m1, std::vector<TileDev> &out, int kBand = 4)
 {
     std::vector<TileDev> order;
     for (int p = 0; p < (int)np_tiles.size(); ++p) {
@@ -293,7 +320,7 @@ void build_tiles(const std::vector<int> &np_tiles, int mats, std::vector<TileDev
         for (int b0 = 0; b0 < nt; b0 += kBand)
             for (int tj = b0; tj < nt; ++tj)
                 for (int ti = b0; ti < std::min(b0 + kBand, tj + 1); ++ti)
-                    for (int m = 0; m < mats; ++m) order.push_back(TileDev{p, ti, tj, m});
+                    for (int m = m0; m < m1; ++m) order.push_back(TileDev{p, ti, tj, m});
     }
     const int n = (int)order.size();
     out.resize(n);
@@ -363,7 +390,7 @@ flapw_status run_split(flapw_handle h, const std::vector<SplitProblemDev> &probs
                        int band, hipStream_t st)
 {
     std::vector<TileDev> tiles;
-    build_tiles(npt, 2, tiles, band);
+    build_tiles(npt, 0, 2, tiles, band);
     auto &hb = h->host_sdesc;
     hb.clear();
     const size_t op = put(hb, probs.data(), probs.size());
@@ -383,7 +410,7 @@ flapw_status run_fp64(flapw_handle h, const std::vector<ProblemDev> &probs_in, c
                       hipStream_t s)
 {
     std::vector<TileDev> tiles;
-    build_tiles(npt, 1, tiles, band);
+    build_tiles(npt, 0, 1, tiles, band);
     auto &hb = h->host_tiles;
     hb.clear();
     const size_t op = put(hb, probs_in.data(), probs_in.size());
@@ -392,7 +419,7 @@ flapw_status run_fp64(flapw_handle h, const std::vector<ProblemDev> &probs_in, c
     if (st != FLAPW_OK) return st;
     unsigned char *base = (unsigned char *)h->tiles.p;
     ProfScope prof(h, "hs_fp64", s);
-    hipError_t e = launch_hs_fp64((const ProblemDev *)(base + op), (const TileDev *)(base + ot), (int)tiles.size(), s);
+    hipError_t e = launch_hs_fp64((const ProblemDev *)(base + op), (const TileDev *)(base + ot), (int)tiles.size(), true, s);
     if (e != hipSuccess) return dev_fail(h, e, "S/H FP64 kernel");
     return FLAPW_OK;
 }
@@ -413,6 +440,8 @@ struct GenPlan {
     Layout L;
     int n_k = 0;
     bool split = false;
+    bool leg = false;            // S through the addition theorem; the contraction computes H only
+    double omega = 0.0;
     int sl = 0, band = 4;
     long long ldt = 0;
     double pref = 0.0;
@@ -421,18 +450,47 @@ struct GenPlan {
     std::vector<const double *> g;
     std::vector<int> ng;
     std::vector<long long> np;
+    std::vector<flapw_z *> S;
+    std::vector<long long> ldh;
     std::vector<size_t> off;     // per k-point: byte offset of its P/Q (FP64) or digits (split)
     GauntPlan gp;
     size_t oa = 0, ot = 0, od = 0, oty = 0, onl = 0, orow = 0;
+    size_t oapos = 0, olrow = 0, olrng = 0;                  // Legendre tables
+    std::vector<size_t> o_stiles;                            // Legendre S tiles of each k-point
+    std::vector<int> n_stiles;
     std::vector<GenBatch> batches;
     double2 *T = nullptr;
     unsigned char *tables = nullptr, *gaunt = nullptr, *desc = nullptr, *work = nullptr, *digits = nullptr;
+    unsigned char *legbuf = nullptr;                         // khat, ab, E of one k-point
+    size_t leg_ab = 0, leg_E = 0;                            // byte offsets inside `leg`
 };
 
 struct GenBuffers {
-    DevBuf *tmat, *tables, *gaunt, *desc, *work, *digits;
+    DevBuf *tmat, *tables, *gaunt, *desc, *work, *digits, *leg;
     std::vector<unsigned char> *h_tables, *h_gaunt, *h_desc;
 };
+
+// Legendre scratch of one k-point with np columns: khat, ab, E (each 256-byte aligned).
+size_t leg_bytes(const Layout &L, long long np, int n_types, size_t *o_ab, size_t *o_E)
+{
+    const size_t khat = round_up(np * 32, 256);
+    const size_t ab = round_up((long long)n_types * kLStride * np * 32, 256);
+    *o_ab = khat;
+    *o_E = khat + ab;
+    return khat + ab + round_up(np * L.ldE * 16, 256);
+}
+
+// Upper-triangle tile list (ti, tj) of an np x np matrix for the Legendre S kernel.
+void s_tiles(long long np, std::vector<int> &out)
+{
+    const int nt = (int)(np / kTile);
+    out.clear();
+    for (int tj = 0; tj < nt; ++tj)
+        for (int ti = 0; ti <= tj; ++ti) {
+            out.push_back(ti);
+            out.push_back(tj);
+        }
+}
 
 flapw_status put_device(flapw_handle h, DevBuf &dst, const std::vector<unsigned char> &src, hipStream_t s, bool sync)
 {
@@ -447,11 +505,13 @@ flapw_status put_device(flapw_handle h, DevBuf &dst, const std::vector<unsigned 
 flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const int *n_g, const double *const *g,
                               const flapw_atoms *at, const flapw_radial *rad, const flapw_potential *pot,
                               flapw_z *const *H, flapw_z *const *S, const long *ldh, flapw_prec prec, int slices,
-                              int band, GenBuffers &b, GenPlan &p, hipStream_t s, bool sync_upload)
+                              int band, bool leg, GenBuffers &b, GenPlan &p, hipStream_t s, bool sync_upload)
 {
     Layout &L = p.L;
     build_layout(at, rad, true, L);
     p.n_k = n_k;
+    p.leg = leg;
+    p.omega = at->omega;
     p.n_atoms = at->n_atoms;
     p.n_types = rad->n_types;
     p.split = prec != FLAPW_PREC_FP64;
@@ -462,6 +522,8 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     p.kv.assign(k, k + 3 * (size_t)n_k);
     p.g.assign(g, g + n_k);
     p.ng.assign(n_g, n_g + n_k);
+    p.S.assign(S, S + n_k);
+    p.ldh.assign(ldh, ldh + n_k);
     p.np.resize(n_k);
     for (int i = 0; i < n_k; ++i) p.np[i] = round_up(n_g[i], kTile);
 
@@ -481,6 +543,9 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     p.oty = put(ht, L.atom_type.data(), L.atom_type.size());
     p.onl = put(ht, L.atom_nl2.data(), L.atom_nl2.size());
     p.orow = put(ht, L.atom_row.data(), L.atom_row.size());
+    p.oapos = put(ht, L.apos.data(), L.apos.size());
+    p.olrow = put(ht, L.leg_row.data(), L.leg_row.size());
+    p.olrng = put(ht, L.leg_ranges.data(), L.leg_ranges.size());
     if ((st = put_device(h, *b.tables, ht, s, sync_upload)) != FLAPW_OK) return st;
     p.tables = (unsigned char *)b.tables->p;
 
@@ -524,10 +589,25 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
         if ((e = b.work->ensure(biggest)) != hipSuccess) return dev_fail(h, e, "allocating work buffer");
     }
     p.work = (unsigned char *)b.work->p;
+    if (p.leg) {
+        const size_t lb = leg_bytes(L, np_max, p.n_types, &p.leg_ab, &p.leg_E);
+        if ((e = b.leg->ensure(lb)) != hipSuccess) return dev_fail(h, e, "allocating Legendre scratch");
+        p.legbuf = (unsigned char *)b.leg->p;
+    }
 
     // contraction descriptors of every batch
     auto &hd = *b.h_desc;
     hd.clear();
+    if (p.leg) {
+        p.o_stiles.resize(n_k);
+        p.n_stiles.resize(n_k);
+        std::vector<int> tl;
+        for (int i = 0; i < n_k; ++i) {
+            s_tiles(p.np[i], tl);
+            p.o_stiles[i] = put(hd, tl.data(), tl.size());
+            p.n_stiles[i] = (int)tl.size() / 2;
+        }
+    }
     for (auto &bt : p.batches) {
         std::vector<int> npt;
         std::vector<ProblemDev> probs;
@@ -545,13 +625,38 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
             }
         }
         std::vector<TileDev> tiles;
-        build_tiles(npt, p.split ? 2 : 1, tiles, p.band);
+        if (p.split) build_tiles(npt, p.leg ? 1 : 0, 2, tiles, p.band);
+        else build_tiles(npt, 0, 1, tiles, p.band);
         bt.o_probs = p.split ? put(hd, sprobs.data(), sprobs.size()) : put(hd, probs.data(), probs.size());
         bt.o_tiles = put(hd, tiles.data(), tiles.size());
         bt.n_tiles = (int)tiles.size();
     }
     if ((st = put_device(h, *b.desc, hd, s, sync_upload)) != FLAPW_OK) return st;
     p.desc = (unsigned char *)b.desc->p;
+    return FLAPW_OK;
+}
+
+// S of k-point i through the addition theorem (prep kernel, then the tile kernel).
+flapw_status enqueue_s_legendre(flapw_handle h, const GenPlan &p, int i, double2 *S, long long lds, hipStream_t s)
+{
+    const Layout &L = p.L;
+    double *khat = (double *)p.legbuf, *ab = (double *)(p.legbuf + p.leg_ab);
+    double2 *E = (double2 *)(p.legbuf + p.leg_E);
+    hipError_t e;
+    {
+        ProfScope prof(h, "leg_prep", s);
+        e = launch_legendre_prep(p.kv.data() + 3 * i, p.ng[i], (int)p.np[i], p.g[i], (const TypeDev *)(p.tables + p.ot),
+                                 p.n_types, (const double *)(p.tables + p.oapos), (const int *)(p.tables + p.olrow),
+                                 p.n_atoms, khat, ab, E, L.ldE, s);
+    }
+    if (e != hipSuccess) return dev_fail(h, e, "Legendre preparation kernel");
+    {
+        ProfScope prof(h, "s_legendre", s);
+        e = launch_s_legendre(khat, ab, E, L.ldE, (const LegTypeRange *)(p.tables + p.olrng), p.n_types,
+                              (const int *)(p.desc + p.o_stiles[i]), p.n_stiles[i], (int)p.np[i], p.ng[i],
+                              4.0 * kPi / p.omega, S, lds, s);
+    }
+    if (e != hipSuccess) return dev_fail(h, e, "Legendre S kernel");
     return FLAPW_OK;
 }
 
@@ -585,6 +690,7 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
                                     (int)L.kp2};
                 if ((st = slice_problem(h, pd, p.np[i], p.sl, da, s)) != FLAPW_OK) return st;
             }
+            if (p.leg && (st = enqueue_s_legendre(h, p, i, (double2 *)p.S[i], p.ldh[i], s)) != FLAPW_OK) return st;
         }
         hipError_t e;
         if (p.split) {
@@ -594,7 +700,7 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
         } else {
             ProfScope prof(h, "hs_fp64", s);
             e = launch_hs_fp64((const ProblemDev *)(p.desc + bt.o_probs), (const TileDev *)(p.desc + bt.o_tiles), bt.n_tiles,
-                               s);
+                               !p.leg, s);
         }
         if (e != hipSuccess) return dev_fail(h, e, p.split ? "S/H split-precision kernel" : "S/H FP64 kernel");
     }
@@ -642,7 +748,7 @@ flapw_status time_contraction(flapw_handle h, const GenPlan &p, int cap, float *
             e = p.split ? launch_split_contract((const SplitProblemDev *)(p.desc + bt.o_probs),
                                                 (const TileDev *)(p.desc + bt.o_tiles), n, p.sl, nullptr)
                         : launch_hs_fp64((const ProblemDev *)(p.desc + bt.o_probs), (const TileDev *)(p.desc + bt.o_tiles),
-                                         n, nullptr);
+                                         n, !p.leg, nullptr);
         if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
@@ -721,6 +827,7 @@ flapw_status flapw_destroy(flapw_handle h)
     h->tables.release();
     h->gaunt.release();
     h->tiles.release();
+    h->leg.release();
     split_release(h);
     delete h;
     return FLAPW_OK;
@@ -759,8 +866,8 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
     TuneScratch scratch;
     hipError_t e;
     int chosen = 0;
-    GenBuffers b{&h->tmat, &h->tables, &h->gaunt, &h->tiles, &h->work, &h->digits, &h->host_tables, &h->host_gaunt,
-                 &h->host_tiles};
+    GenBuffers b{&h->tmat,        &h->tables,      &h->gaunt,     &h->tiles,     &h->work, &h->digits,
+                 &h->leg,         &h->host_tables, &h->host_gaunt, &h->host_tiles};
     if (split) {
         // accuracy gate on the first n_acc columns (the shortest k+G), against the FP64 path
         const int n_acc = std::min(n_g, 1024);
@@ -773,7 +880,7 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
         for (int s = 0; s <= 6; s = s ? s + 1 : 3) {          // s = 0 (FP64 reference), then 3..6 digits
             flapw_z *Hp = (flapw_z *)buf[s ? 2 : 0], *Sp = (flapw_z *)buf[s ? 3 : 1];
             GenPlan p;
-            st = prepare_generate(h, 1, k, &n_acc, &g, at, rad, pot, &Hp, &Sp, &ldn, s ? prec : FLAPW_PREC_FP64, s, 4, b,
+            st = prepare_generate(h, 1, k, &n_acc, &g, at, rad, pot, &Hp, &Sp, &ldn, s ? prec : FLAPW_PREC_FP64, s, 4, false, b,
                                   p, nullptr, false);
             if (st == FLAPW_OK) st = enqueue_generate(h, p, nullptr);
             if (st != FLAPW_OK) return st;
@@ -798,7 +905,8 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
     for (int i = 0; i < 5; ++i) {
         flapw_z *Hp = (flapw_z *)Hb, *Sp = (flapw_z *)Sb;
         GenPlan p;
-        st = prepare_generate(h, 1, k, &n_g, &g, at, rad, pot, &Hp, &Sp, &ld1, prec, chosen, bands[i], b, p, nullptr,
+        st = prepare_generate(h, 1, k, &n_g, &g, at, rad, pot, &Hp, &Sp, &ld1, prec, chosen, bands[i],
+                              h->s_method == FLAPW_S_LEGENDRE, b, p, nullptr,
                               false);
         if (st == FLAPW_OK && i == 0) st = enqueue_generate(h, p, nullptr);   // panels / digits for the timing
         if (st != FLAPW_OK) return st;
@@ -837,7 +945,8 @@ flapw_status flapw_profile_query(flapw_handle h, const char *family, int *launch
 {
     if (!h) return FLAPW_ERR_ARG;
     if (!family || !launches || !total_ms) return fail(h, FLAPW_ERR_ARG, "NULL argument");
-    static const char *known[] = {"coeffs", "tmat", "qpanel", "repack", "hs_fp64", "slice", "hs_split", "graph"};
+    static const char *known[] = {"coeffs", "tmat",  "qpanel",   "repack",     "hs_fp64",
+                                  "slice",  "hs_split", "graph", "leg_prep", "s_legendre"};
     bool ok = false;
     for (const char *k : known) ok = ok || std::strcmp(k, family) == 0;
     if (!ok) return fail(h, FLAPW_ERR_ARG, std::string("unknown kernel family ") + family);
@@ -861,7 +970,7 @@ flapw_status flapw_profile_query(flapw_handle h, const char *family, int *launch
 long long flapw_workspace_bytes(flapw_handle h)
 {
     if (!h) return -1;
-    return (long long)(h->work.n + h->tmat.n + h->tables.n + h->gaunt.n + h->tiles.n) + split_bytes(h);
+    return (long long)(h->work.n + h->tmat.n + h->tables.n + h->gaunt.n + h->tiles.n + h->leg.n) + split_bytes(h);
 }
 
 flapw_status flapw_coeffs(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
@@ -992,11 +1101,67 @@ flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const i
     if (st != FLAPW_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     GenPlan p;
-    GenBuffers b{&h->tmat, &h->tables, &h->gaunt, &h->tiles, &h->work, &h->digits, &h->host_tables, &h->host_gaunt,
-                 &h->host_tiles};
-    st = prepare_generate(h, n_k, k, n_g, g, at, rad, pot, H, S, ldh, prec, slices, 0, b, p, s, false);
+    GenBuffers b{&h->tmat,        &h->tables,      &h->gaunt,     &h->tiles,     &h->work, &h->digits,
+                 &h->leg,         &h->host_tables, &h->host_gaunt, &h->host_tiles};
+    st = prepare_generate(h, n_k, k, n_g, g, at, rad, pot, H, S, ldh, prec, slices, 0, h->s_method == FLAPW_S_LEGENDRE,
+                          b, p, s, false);
     if (st != FLAPW_OK) return st;
     return enqueue_generate(h, p, s);
+}
+
+flapw_status flapw_set_s_method(flapw_handle h, flapw_s_method method)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    if (method != FLAPW_S_GEMM && method != FLAPW_S_LEGENDRE) return fail(h, FLAPW_ERR_ARG, "unknown S method");
+    h->s_method = (int)method;
+    return FLAPW_OK;
+}
+
+flapw_status flapw_s_legendre(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
+                              const flapw_radial *rad, flapw_z *S, long lds, flapw_stream stream)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    if (!k || !g || !S) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
+    if (n_g < 1) return fail(h, FLAPW_ERR_ARG, "n_g must be >= 1");
+    if (lds < n_g) return fail(h, FLAPW_ERR_ARG, "lds < n_g");
+    if (!finite_all(k, 3)) return fail(h, FLAPW_ERR_ARG, "non-finite k");
+    flapw_status st = check_radial(h, rad);
+    if (st != FLAPW_OK) return st;
+    if ((st = check_atoms(h, at, rad, true)) != FLAPW_OK) return st;
+    if (!(at->omega > 0.0)) return fail(h, FLAPW_ERR_ARG, "omega must be > 0");
+    if (h->device < 0) return fail(h, FLAPW_ERR_DEVICE, "no HIP device");
+    hipStream_t s = (hipStream_t)stream;
+    GenPlan p;
+    Layout &L = p.L;
+    build_layout(at, rad, true, L);
+    p.leg = true;
+    p.omega = at->omega;
+    p.n_atoms = at->n_atoms;
+    p.n_types = rad->n_types;
+    p.kv.assign(k, k + 3);
+    p.g.assign(1, g);
+    p.ng.assign(1, n_g);
+    p.np.assign(1, round_up(n_g, kTile));
+    auto &ht = h->host_tables;
+    ht.clear();
+    p.ot = put(ht, L.types.data(), L.types.size());
+    p.oapos = put(ht, L.apos.data(), L.apos.size());
+    p.olrow = put(ht, L.leg_row.data(), L.leg_row.size());
+    p.olrng = put(ht, L.leg_ranges.data(), L.leg_ranges.size());
+    if ((st = upload(h, h->tables, ht, s)) != FLAPW_OK) return st;
+    p.tables = (unsigned char *)h->tables.p;
+    std::vector<int> tl;
+    s_tiles(p.np[0], tl);
+    auto &hd = h->host_tiles;
+    hd.clear();
+    p.o_stiles.assign(1, put(hd, tl.data(), tl.size()));
+    p.n_stiles.assign(1, (int)tl.size() / 2);
+    if ((st = upload(h, h->tiles, hd, s)) != FLAPW_OK) return st;
+    p.desc = (unsigned char *)h->tiles.p;
+    hipError_t e = h->leg.ensure(leg_bytes(L, p.np[0], p.n_types, &p.leg_ab, &p.leg_E));
+    if (e != hipSuccess) return dev_fail(h, e, "allocating Legendre scratch");
+    p.legbuf = (unsigned char *)h->leg.p;
+    return enqueue_s_legendre(h, p, 0, (double2 *)S, lds, s);
 }
 
 flapw_status flapw_plan_create(flapw_handle h, int n_k, const double *k, const int *n_g, const double *const *g,
@@ -1011,14 +1176,16 @@ flapw_status flapw_plan_create(flapw_handle h, int n_k, const double *k, const i
     if (st != FLAPW_OK) return st;
     hipError_t e = init_fp64_kernels();
     if (e == hipSuccess && prec != FLAPW_PREC_FP64) e = init_split_kernels();
+    if (e == hipSuccess && h->s_method == FLAPW_S_LEGENDRE) e = init_legendre_kernels();
     if (e != hipSuccess) return dev_fail(h, e, "kernel attributes");
     flapw_plan_s *pl = new (std::nothrow) flapw_plan_s();
     if (!pl) return fail(h, FLAPW_ERR_NOMEM, "plan allocation");
     pl->h = h;
     GenPlan p;
-    GenBuffers b{&pl->tmat, &pl->tables, &pl->gaunt, &pl->desc, &pl->work, &pl->digits, &pl->h_tables, &pl->h_gaunt,
-                 &pl->h_desc};
-    st = prepare_generate(h, n_k, k, n_g, g, at, rad, pot, H, S, ldh, prec, slices, 0, b, p, nullptr, true);
+    GenBuffers b{&pl->tmat, &pl->tables, &pl->gaunt, &pl->desc, &pl->work, &pl->digits, &pl->leg, &pl->h_tables,
+                 &pl->h_gaunt, &pl->h_desc};
+    st = prepare_generate(h, n_k, k, n_g, g, at, rad, pot, H, S, ldh, prec, slices, 0, h->s_method == FLAPW_S_LEGENDRE,
+                          b, p, nullptr, true);
     hipStream_t cs = nullptr;
     if (st == FLAPW_OK) {
         e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -1072,6 +1239,7 @@ flapw_status flapw_plan_destroy(flapw_plan plan)
     plan->tables.release();
     plan->gaunt.release();
     plan->desc.release();
+    plan->leg.release();
     delete plan;
     return FLAPW_OK;
 }

@@ -23,6 +23,7 @@ struct AtomDev {
 struct RadialDev {
     double u, du, ud, dud;
     double inv_w;         // 1 / W, W = udot u' - u udot'
+    double ud_norm2;      // ||udot_l||^2
 };
 
 constexpr int kMaxTypes = 64;
@@ -89,7 +90,8 @@ hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, con
                          const long long *atom_row, int n_atoms, const double2 *P, double2 *Q, long long ldp, int np,
                          hipStream_t s);
 
-hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_tiles, hipStream_t s);
+// with_s = false: H alone (S tiles of the problems are not touched)
+hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_tiles, bool with_s, hipStream_t s);
 
 hipError_t launch_repack(const double2 *A, const double2 *B, long long lda, int n_g, const AtomDev *atoms,
                          int n_atoms, const long long *src_off, double2 *P, long long ldp, int kp2, int np,
@@ -104,6 +106,24 @@ hipError_t launch_split_slice(const double2 *P, const double2 *Q, const double *
                               hipStream_t s);
 hipError_t launch_split_contract(const SplitProblemDev *probs, const TileDev *tiles, int n_tiles, int slices,
                                  hipStream_t s);
+
+// Overlap matrix through the addition theorem (legendre.hip).
+//   khat : np x 4 doubles (unit K_t), ab : n_types x kLStride x np x 4 doubles {alpha, beta, ||udot||^2 beta, 0},
+//   E    : np columns of ldE complex phases exp(i K_t.x_a), rows grouped by type.
+struct LegTypeRange {
+    int row0;             // first row of the type's atoms in E
+    int rows;             // rows of the type (multiple of 16; padding rows hold zeros)
+    int lmax;
+    int pad;
+};
+hipError_t init_legendre_kernels();
+hipError_t launch_legendre_prep(const double kvec[3], int n_g, int np, const double *g, const TypeDev *types,
+                                int n_types, const double *apos, const int *arow, int n_atoms, double *khat,
+                                double *ab, double2 *E, long long ldE, hipStream_t s);
+// tiles: n_tiles (ti, tj) pairs with ti <= tj; S written on the upper triangle, scale = 4 pi / Omega
+hipError_t launch_s_legendre(const double *khat, const double *ab, const double2 *E, long long ldE,
+                             const LegTypeRange *ranges, int n_types, const int *tiles, int n_tiles, int np, int n,
+                             double scale, double2 *S, long long lds, hipStream_t s);
 
 constexpr int kTile = 64;     // output tile edge (complex elements) of the contraction kernels
 constexpr int kKTile = 16;    // contraction rows per pipeline stage (FP64 kernels)

@@ -59,6 +59,8 @@ struct flapw_context {
     flapw::DevBuf tiles;       // problem descriptors and tile list of a contraction launch
     flapw::DevBuf digits;      // split precision: digit planes and column exponents
     flapw::DevBuf sdesc;       // split precision: descriptors
+    flapw::DevBuf leg;         // S through the addition theorem: Khat, radial factors, phases of one k-point
+    int s_method = 0;          // flapw_s_method of flapw_hs_generate and flapw_plan_create
     std::vector<unsigned char> host_tables, host_gaunt, host_tiles, host_sdesc;
     std::vector<long long> host_src;
     // tuning (flapw_tune): chosen digit count and tile band per (precision, padded contraction rows)
@@ -78,7 +80,7 @@ struct flapw_context {
 // A captured S/H generation (flapw_plan_create): its own device buffers and the graph.
 struct flapw_plan_s {
     flapw_handle h = nullptr;
-    flapw::DevBuf work, digits, tmat, tables, gaunt, desc;
+    flapw::DevBuf work, digits, tmat, tables, gaunt, desc, leg;
     std::vector<unsigned char> h_tables, h_gaunt, h_desc;
     hipGraphExec_t exec = nullptr;
 };

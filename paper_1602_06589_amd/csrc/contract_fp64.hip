@@ -93,10 +93,13 @@ constexpr int kHsThreads = 512;             // 8 waves: two per SIMD, splitting 
 // Eight waves: wave w owns quadrant (w & 3) of the 64 x 64 tile (2 x 2 MFMA blocks) and the
 // k-steps {0, 8} (w < 4) or {4, 12} (w >= 4) of every 16-row stage, so two waves per SIMD
 // keep the FP64 matrix core busy across barriers and LDS waits.  Their partial sums are
-// added through LDS at the end; waves 0-3 then store S, waves 4-7 store H.
+// added through LDS at the end; with S, waves 0-3 then store S and waves 4-7 store H.
+// WITH_S = false computes H alone (S comes from another method) and stages no d.P panel.
+template <bool WITH_S>
 __global__ __launch_bounds__(kHsThreads, 1) void hs_fp64_kernel(const ProblemDev *__restrict__ probs,
                                                                 const TileDev *__restrict__ tiles)
 {
+    constexpr int NM = WITH_S ? 2 : 1;                 // matrices: [S,] H
     extern __shared__ __align__(16) unsigned char smem_raw[];
     HsSmem &sm = *reinterpret_cast<HsSmem *>(smem_raw);
 
@@ -113,9 +116,9 @@ __global__ __launch_bounds__(kHsThreads, 1) void hs_fp64_kernel(const ProblemDev
     gdouble2 *gQ = (gdouble2 *)pb.Q + (j0 + lc) * pb.ldp + lk;
     gdouble *gd = (gdouble *)pb.d + lk;
 
-    v4d acc[2][2][2][2];                               // [S, H][re, im][mi][ni]
+    v4d acc[NM][2][2][2];                              // [S,] H x [re, im][mi][ni]
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NM; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -131,15 +134,19 @@ __global__ __launch_bounds__(kHsThreads, 1) void hs_fp64_kernel(const ProblemDev
     do {                                                                \
         const long long off_ = (long long)(kt) * kKTile;                \
         l0 = gL[off_]; l1 = gL[off_ + 1];                               \
-        r0 = gR[off_]; r1 = gR[off_ + 1];                               \
+        if (WITH_S) {                                                   \
+            r0 = gR[off_]; r1 = gR[off_ + 1];                           \
+            d0 = gd[off_]; d1 = gd[off_ + 1];                           \
+        }                                                               \
         q0 = gQ[off_]; q1 = gQ[off_ + 1];                               \
-        d0 = gd[off_]; d1 = gd[off_ + 1];                               \
     } while (0)
 #define HS_STORE(b)                                                                              \
     do {                                                                                         \
         double2 *sl_ = &sm.v[b][0][lc][lk], *sr_ = &sm.v[b][1][lc][lk], *sq_ = &sm.v[b][2][lc][lk]; \
         sl_[0] = l0; sl_[1] = l1;                                                                \
-        sr_[0] = make_double2(r0.x * d0, r0.y * d0); sr_[1] = make_double2(r1.x * d1, r1.y * d1); \
+        if (WITH_S) {                                                                            \
+            sr_[0] = make_double2(r0.x * d0, r0.y * d0); sr_[1] = make_double2(r1.x * d1, r1.y * d1); \
+        }                                                                                        \
         sq_[0] = q0; sq_[1] = q1;                                                                \
     } while (0)
 
@@ -150,8 +157,13 @@ __global__ __launch_bounds__(kHsThreads, 1) void hs_fp64_kernel(const ProblemDev
     for (int kt = 0; kt < nkt; ++kt) {
         const int b = kt & 1;
         if (kt + 1 < nkt) HS_LOAD(kt + 1);
-        if (khalf == 0) stage_mma<2, 0, 8>(sm.v[b][0], sm.v[b][1], sm.v[b][2], wm, wn, lane, acc);
-        else            stage_mma<2, 4, 8>(sm.v[b][0], sm.v[b][1], sm.v[b][2], wm, wn, lane, acc);
+        if (WITH_S) {
+            if (khalf == 0) stage_mma<NM, 0, 8>(sm.v[b][0], sm.v[b][1], sm.v[b][2], wm, wn, lane, acc);
+            else            stage_mma<NM, 4, 8>(sm.v[b][0], sm.v[b][1], sm.v[b][2], wm, wn, lane, acc);
+        } else {
+            if (khalf == 0) stage_mma<NM, 0, 8>(sm.v[b][0], sm.v[b][2], sm.v[b][2], wm, wn, lane, acc);
+            else            stage_mma<NM, 4, 8>(sm.v[b][0], sm.v[b][2], sm.v[b][2], wm, wn, lane, acc);
+        }
         if (kt + 1 < nkt) HS_STORE(b ^ 1);
         __syncthreads();
     }
@@ -159,11 +171,11 @@ __global__ __launch_bounds__(kHsThreads, 1) void hs_fp64_kernel(const ProblemDev
 #undef HS_STORE
 
     // add the two halves: S partials of waves 4-7 to waves 0-3, then H partials the other way
+    // (H alone: waves 4-7 to waves 0-3)
     double *xch = reinterpret_cast<double *>(smem_raw);   // [quadrant][32 values][64 lanes]
 #pragma unroll
-    for (int round = 0; round < 2; ++round) {
-        const int mat = round;                              // 0: S, 1: H
-        const bool sender = (round == 0) ? (khalf == 1) : (khalf == 0);
+    for (int mat = 0; mat < NM; ++mat) {
+        const bool sender = (mat == 0) ? (khalf == 1) : (khalf == 0);
         if (sender) {
 #pragma unroll
             for (int c = 0; c < 2; ++c)
@@ -191,8 +203,9 @@ __global__ __launch_bounds__(kHsThreads, 1) void hs_fp64_kernel(const ProblemDev
     }
 
     // epilogue: upper triangle (row <= col < n); diagonal imaginary part set to zero
-    const int mat = khalf;                                  // waves 0-3 store S, waves 4-7 store H
-    double2 *out = mat == 0 ? pb.S : pb.H;
+    const int mat = WITH_S ? khalf : 0;                     // with S: waves 0-3 store S, waves 4-7 H
+    if (!WITH_S && khalf == 1) return;
+    double2 *out = (WITH_S && mat == 0) ? pb.S : pb.H;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -202,8 +215,8 @@ __global__ __launch_bounds__(kHsThreads, 1) void hs_fp64_kernel(const ProblemDev
                 const long long row = i0 + wm + mi * 16 + (lane >> 4) + 4 * r;
                 const long long col = j0 + wn + ni * 16 + (lane & 15);
                 if (row <= col && col < pb.n) {
-                    const double re = mat == 0 ? acc[0][0][mi][ni][r] : acc[1][0][mi][ni][r];
-                    const double im = mat == 0 ? acc[0][1][mi][ni][r] : acc[1][1][mi][ni][r];
+                    const double re = mat == 0 ? acc[0][0][mi][ni][r] : acc[NM - 1][0][mi][ni][r];
+                    const double im = mat == 0 ? acc[0][1][mi][ni][r] : acc[NM - 1][1][mi][ni][r];
                     out[col * pb.ldh + row] = make_double2(re, row == col ? 0.0 : im);
                 }
             }
@@ -312,8 +325,11 @@ hipError_t init_fp64_kernels()
 {
     static hipError_t done = hipErrorNotReady;
     if (done == hipSuccess) return done;
-    hipError_t e = hipFuncSetAttribute((const void *)hs_fp64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void *)hs_fp64_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)sizeof(HsSmem));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)hs_fp64_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sizeof(HsSmem));
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)qpanel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sizeof(QSmem));
@@ -321,11 +337,14 @@ hipError_t init_fp64_kernels()
     return e;
 }
 
-hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_tiles, hipStream_t s)
+hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_tiles, bool with_s, hipStream_t s)
 {
     hipError_t e = init_fp64_kernels();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(hs_fp64_kernel, dim3(n_tiles), dim3(kHsThreads), sizeof(HsSmem), s, probs, tiles);
+    if (with_s)
+        hipLaunchKernelGGL(hs_fp64_kernel<true>, dim3(n_tiles), dim3(kHsThreads), sizeof(HsSmem), s, probs, tiles);
+    else
+        hipLaunchKernelGGL(hs_fp64_kernel<false>, dim3(n_tiles), dim3(kHsThreads), sizeof(HsSmem), s, probs, tiles);
     return hipGetLastError();
 }
 

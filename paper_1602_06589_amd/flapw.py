@@ -28,12 +28,14 @@ LIB_PATH = os.path.join(_HERE, "libflapw_hip.so")
 
 FP64, SPLIT_BF16, SPLIT_I8 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "bf16": SPLIT_BF16, "i8": SPLIT_I8}
+S_METHODS = {"gemm": 0, "legendre": 1}
 
 _STATUS = {0: "FLAPW_OK", -1: "FLAPW_ERR_ARG", -2: "FLAPW_ERR_WRONSKIAN", -3: "FLAPW_ERR_NOT_HERMITIAN",
            -4: "FLAPW_ERR_NOMEM", -5: "FLAPW_ERR_DEVICE", -6: "FLAPW_ERR_UNSUPPORTED"}
 
 EXPORTS = ["flapw_create", "flapw_destroy", "flapw_status_string", "flapw_last_error", "flapw_workspace_bytes",
-           "flapw_coeffs", "flapw_build_T", "flapw_hs_contract", "flapw_hs_generate", "flapw_plan_create",
+           "flapw_coeffs", "flapw_build_T", "flapw_hs_contract", "flapw_hs_generate", "flapw_set_s_method",
+           "flapw_s_legendre", "flapw_plan_create",
            "flapw_plan_launch", "flapw_plan_destroy", "flapw_tune", "flapw_profile_enable", "flapw_profile_query"]
 
 
@@ -82,6 +84,8 @@ def load_library(path: str = LIB_PATH):
         lib.flapw_build_T.argtypes = [P, P, P, P, L, P]
         lib.flapw_hs_contract.argtypes = [P, I, P, P, P, P, L, P, L, P, P, L, I, I, P]
         lib.flapw_hs_generate.argtypes = [P, I, P, P, P, P, P, P, P, P, P, I, I, P]
+        lib.flapw_set_s_method.argtypes = [P, I]
+        lib.flapw_s_legendre.argtypes = [P, P, I, P, P, P, P, L, P]
         lib.flapw_plan_create.argtypes = [P, I, P, P, P, P, P, P, P, P, P, I, I, ctypes.POINTER(P)]
         lib.flapw_plan_launch.argtypes = [P, P]
         lib.flapw_plan_destroy.argtypes = [P]
@@ -235,6 +239,24 @@ class Flapw:
                                                 int(H.shape[1]), PRECISIONS.get(prec, prec), int(slices),
                                                 _stream(stream)))
         return H, S
+
+    def set_s_method(self, method: str = "gemm"):
+        """How hs_generate and plan compute S: "gemm" (with H on the matrix cores, in the chosen
+        precision) or "legendre" (addition theorem, FP64; the contraction then computes H only)."""
+        self._check(self._lib.flapw_set_s_method(self._h, S_METHODS.get(method, method)))
+
+    def s_legendre(self, system, k, g, S=None, stream=None):
+        """S of one k-point through the addition theorem.  g: device tensor (n_g, 3)."""
+        import torch
+        self._keep = []
+        n_g = int(g.shape[0])
+        if S is None:
+            S = torch.zeros((n_g, n_g), dtype=torch.complex128, device=g.device)
+        kk = _f64(k)
+        rad, at = self._radial(system), self._atoms(system)
+        self._check(self._lib.flapw_s_legendre(self._h, _ptr(kk), n_g, _dptr(g), ctypes.byref(at), ctypes.byref(rad),
+                                               _dptr(S), int(S.shape[1]), _stream(stream)))
+        return S
 
     def _generate_args(self, system, kpts, gvecs, out):
         import torch
