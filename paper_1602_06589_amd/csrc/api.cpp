@@ -331,7 +331,10 @@ void build_tiles(const std::vector<int> &np_tiles, int m0, int m1, std::vector<T
     for (int b = 0; b < n; ++b) out[b] = order[start[b % 8] + b / 8];
 }
 
-int default_slices(flapw_prec prec) { return prec == FLAPW_PREC_SPLIT_I8 ? 6 : 5; }
+int default_slices(flapw_prec) { return 6; }
+
+// bytes per digit: int8 digits 1, bf16 digits 2
+int digit_bytes(flapw_prec prec) { return prec == FLAPW_PREC_SPLIT_BF16 ? 2 : 1; }
 
 const flapw_context::Tuned *find_tuned(flapw_handle h, flapw_prec prec, long long kp2)
 {
@@ -361,33 +364,42 @@ struct DigitArea {
     int *eL, *eRS, *eRH;
 };
 
-long long digit_area_bytes(long long kp2, long long np, int s)
+long long digit_area_bytes(long long kp2, long long np, int s, int eb)
 {
-    const long long one = round_up(2LL * s * kp2 * np, 256);
+    const long long one = round_up(2LL * s * kp2 * np * eb, 256);
     return 3 * one + 3 * round_up(np * 4, 256);
 }
 
-DigitArea digit_area(void *base, long long kp2, long long np, int s)
+DigitArea digit_area(void *base, long long kp2, long long np, int s, int eb)
 {
-    const long long one = round_up(2LL * s * kp2 * np, 256);
+    const long long one = round_up(2LL * s * kp2 * np * eb, 256);
     const long long ex = round_up(np * 4, 256);
     unsigned char *b = (unsigned char *)base;
     return DigitArea{(int8_t *)b, (int8_t *)(b + one), (int8_t *)(b + 2 * one), (int *)(b + 3 * one),
                      (int *)(b + 3 * one + ex), (int *)(b + 3 * one + 2 * ex)};
 }
 
-flapw_status slice_problem(flapw_handle h, const ProblemDev &pb, long long np, int s, const DigitArea &da,
+flapw_status slice_problem(flapw_handle h, const ProblemDev &pb, long long np, int s, const DigitArea &da, bool bf16,
                            hipStream_t st)
 {
     ProfScope prof(h, "slice", st);
-    hipError_t e = launch_split_slice(pb.P, pb.Q, pb.d, pb.ldp, pb.kp2, (int)np, s, da.eL, da.eRS, da.eRH, da.L,
-                                      da.RS, da.RH, st);
+    hipError_t e = bf16 ? launch_split_bf16_slice(pb.P, pb.Q, pb.d, pb.ldp, pb.kp2, (int)np, s, da.eL, da.eRS, da.eRH,
+                                                  da.L, da.RS, da.RH, st)
+                        : launch_split_slice(pb.P, pb.Q, pb.d, pb.ldp, pb.kp2, (int)np, s, da.eL, da.eRS, da.eRH, da.L,
+                                             da.RS, da.RH, st);
     if (e != hipSuccess) return dev_fail(h, e, "digit slicing kernels");
     return FLAPW_OK;
 }
 
+hipError_t launch_split_any(bool bf16, const SplitProblemDev *probs, const TileDev *tiles, int n_tiles, int s,
+                            hipStream_t st)
+{
+    return bf16 ? launch_split_bf16_contract(probs, tiles, n_tiles, s, st)
+                : launch_split_contract(probs, tiles, n_tiles, s, st);
+}
+
 flapw_status run_split(flapw_handle h, const std::vector<SplitProblemDev> &probs, const std::vector<int> &npt, int s,
-                       int band, hipStream_t st)
+                       int band, bool bf16, hipStream_t st)
 {
     std::vector<TileDev> tiles;
     build_tiles(npt, 0, 2, tiles, band);
@@ -399,8 +411,8 @@ flapw_status run_split(flapw_handle h, const std::vector<SplitProblemDev> &probs
     if (r != FLAPW_OK) return r;
     unsigned char *base = (unsigned char *)h->sdesc.p;
     ProfScope prof(h, "hs_split", st);
-    hipError_t e = launch_split_contract((const SplitProblemDev *)(base + op), (const TileDev *)(base + ot),
-                                         (int)tiles.size(), s, st);
+    hipError_t e = launch_split_any(bf16, (const SplitProblemDev *)(base + op), (const TileDev *)(base + ot),
+                                    (int)tiles.size(), s, st);
     if (e != hipSuccess) return dev_fail(h, e, "S/H split-precision kernel");
     return FLAPW_OK;
 }
@@ -441,6 +453,7 @@ struct GenPlan {
     int n_k = 0;
     bool split = false;
     bool leg = false;            // S through the addition theorem; the contraction computes H only
+    bool bf16 = false;           // split digits in bf16 (else int8)
     double omega = 0.0;
     int sl = 0, band = 4;
     long long ldt = 0;
@@ -515,6 +528,7 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     p.n_atoms = at->n_atoms;
     p.n_types = rad->n_types;
     p.split = prec != FLAPW_PREC_FP64;
+    p.bf16 = prec == FLAPW_PREC_SPLIT_BF16;
     p.sl = effective_slices(h, prec, L.kp2, slices);
     p.band = band ? band : effective_band(h, prec, L.kp2);
     p.ldt = 2LL * L.nlmax;
@@ -564,7 +578,8 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     if (p.split) budget = budget > panel_one ? budget - panel_one : 0;
     std::vector<size_t> need(n_k);
     for (int i = 0; i < n_k; ++i)
-        need[i] = p.split ? (size_t)digit_area_bytes(L.kp2, p.np[i], p.sl) : (size_t)2 * L.kp2 * p.np[i] * sizeof(double2);
+        need[i] = p.split ? (size_t)digit_area_bytes(L.kp2, p.np[i], p.sl, p.bf16 ? 2 : 1)
+                          : (size_t)2 * L.kp2 * p.np[i] * sizeof(double2);
     p.off.assign(n_k, 0);
     size_t biggest = 0;
     for (int i0 = 0; i0 < n_k;) {
@@ -615,7 +630,7 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
         for (int i = bt.i0; i < bt.i1; ++i) {
             npt.push_back((int)(p.np[i] / kTile));
             if (p.split) {
-                const DigitArea da = digit_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl);
+                const DigitArea da = digit_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl, p.bf16 ? 2 : 1);
                 sprobs.push_back(SplitProblemDev{da.L, da.RS, da.RH, da.eL, da.eRS, da.eRH, (double2 *)H[i],
                                                  (double2 *)S[i], (long long)ldh[i], n_g[i], (int)L.kp2});
             } else {
@@ -685,18 +700,18 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
             }
             if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
             if (p.split) {
-                const DigitArea da = digit_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl);
+                const DigitArea da = digit_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl, p.bf16 ? 2 : 1);
                 const ProblemDev pd{P, Q, (const double *)(p.tables + p.od), nullptr, nullptr, L.kp2, 0, p.ng[i],
                                     (int)L.kp2};
-                if ((st = slice_problem(h, pd, p.np[i], p.sl, da, s)) != FLAPW_OK) return st;
+                if ((st = slice_problem(h, pd, p.np[i], p.sl, da, p.bf16, s)) != FLAPW_OK) return st;
             }
             if (p.leg && (st = enqueue_s_legendre(h, p, i, (double2 *)p.S[i], p.ldh[i], s)) != FLAPW_OK) return st;
         }
         hipError_t e;
         if (p.split) {
             ProfScope prof(h, "hs_split", s);
-            e = launch_split_contract((const SplitProblemDev *)(p.desc + bt.o_probs), (const TileDev *)(p.desc + bt.o_tiles),
-                                      bt.n_tiles, p.sl, s);
+            e = launch_split_any(p.bf16, (const SplitProblemDev *)(p.desc + bt.o_probs),
+                                 (const TileDev *)(p.desc + bt.o_tiles), bt.n_tiles, p.sl, s);
         } else {
             ProfScope prof(h, "hs_fp64", s);
             e = launch_hs_fp64((const ProblemDev *)(p.desc + bt.o_probs), (const TileDev *)(p.desc + bt.o_tiles), bt.n_tiles,
@@ -716,9 +731,8 @@ flapw_status check_generate(flapw_handle h, int n_k, const double *k, const int 
     if (prec != FLAPW_PREC_FP64 && prec != FLAPW_PREC_SPLIT_BF16 && prec != FLAPW_PREC_SPLIT_I8)
         return fail(h, FLAPW_ERR_ARG, "unknown precision");
     if (slices < 0 || slices > FLAPW_SLICES_CAP) return fail(h, FLAPW_ERR_ARG, "slices out of range");
-    if (prec == FLAPW_PREC_SPLIT_I8 && slices != 0 && (slices < 3 || slices > 6))
-        return fail(h, FLAPW_ERR_UNSUPPORTED, "int8 split precision supports 3..6 digits");
-    if (prec == FLAPW_PREC_SPLIT_BF16) return fail(h, FLAPW_ERR_UNSUPPORTED, "bf16 split precision is not built");
+    if (prec != FLAPW_PREC_FP64 && slices != 0 && (slices < 3 || slices > 6))
+        return fail(h, FLAPW_ERR_UNSUPPORTED, "split precision supports 3..6 digits");
     for (int i = 0; i < n_k; ++i) {
         if (n_g[i] < 1) return fail(h, FLAPW_ERR_ARG, "n_g must be >= 1");
         if (!g[i] || !H[i] || !S[i]) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
@@ -745,8 +759,8 @@ flapw_status time_contraction(flapw_handle h, const GenPlan &p, int cap, float *
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {     // first launch warms caches and code
         e = hipEventRecord(e0, nullptr);
         if (e == hipSuccess)
-            e = p.split ? launch_split_contract((const SplitProblemDev *)(p.desc + bt.o_probs),
-                                                (const TileDev *)(p.desc + bt.o_tiles), n, p.sl, nullptr)
+            e = p.split ? launch_split_any(p.bf16, (const SplitProblemDev *)(p.desc + bt.o_probs),
+                                           (const TileDev *)(p.desc + bt.o_tiles), n, p.sl, nullptr)
                         : launch_hs_fp64((const ProblemDev *)(p.desc + bt.o_probs), (const TileDev *)(p.desc + bt.o_tiles),
                                          n, !p.leg, nullptr);
         if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
@@ -1027,9 +1041,8 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
     if (prec != FLAPW_PREC_FP64 && prec != FLAPW_PREC_SPLIT_BF16 && prec != FLAPW_PREC_SPLIT_I8)
         return fail(h, FLAPW_ERR_ARG, "unknown precision");
     if (slices < 0 || slices > FLAPW_SLICES_CAP) return fail(h, FLAPW_ERR_ARG, "slices out of range");
-    if (prec == FLAPW_PREC_SPLIT_I8 && slices != 0 && (slices < 3 || slices > 6))
-        return fail(h, FLAPW_ERR_UNSUPPORTED, "int8 split precision supports 3..6 digits");
-    if (prec == FLAPW_PREC_SPLIT_BF16) return fail(h, FLAPW_ERR_UNSUPPORTED, "bf16 split precision is not built");
+    if (prec != FLAPW_PREC_FP64 && slices != 0 && (slices < 3 || slices > 6))
+        return fail(h, FLAPW_ERR_UNSUPPORTED, "split precision supports 3..6 digits");
     flapw_status st = check_radial(h, rad);
     if (st != FLAPW_OK) return st;
     if ((st = check_atoms(h, at, rad, false)) != FLAPW_OK) return st;
@@ -1083,12 +1096,14 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
     const int band = effective_band(h, prec, L.kp2);
     if (prec == FLAPW_PREC_FP64) return run_fp64(h, {pd}, npt, band, s);
     const int sl = effective_slices(h, prec, L.kp2, slices);
-    e = h->digits.ensure((size_t)digit_area_bytes(L.kp2, np, sl));
+    const int eb = digit_bytes(prec);
+    e = h->digits.ensure((size_t)digit_area_bytes(L.kp2, np, sl, eb));
     if (e != hipSuccess) return dev_fail(h, e, "allocating digit buffer");
-    const DigitArea da = digit_area(h->digits.p, L.kp2, np, sl);
-    if ((st = slice_problem(h, pd, np, sl, da, s)) != FLAPW_OK) return st;
+    const DigitArea da = digit_area(h->digits.p, L.kp2, np, sl, eb);
+    const bool bf16 = prec == FLAPW_PREC_SPLIT_BF16;
+    if ((st = slice_problem(h, pd, np, sl, da, bf16, s)) != FLAPW_OK) return st;
     SplitProblemDev sp{da.L, da.RS, da.RH, da.eL, da.eRS, da.eRH, (double2 *)H, (double2 *)S, ldh, n_g, (int)L.kp2};
-    return run_split(h, {sp}, npt, sl, band, s);
+    return run_split(h, {sp}, npt, sl, band, bf16, s);
 }
 
 flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const int *n_g, const double *const *g,
@@ -1175,7 +1190,8 @@ flapw_status flapw_plan_create(flapw_handle h, int n_k, const double *k, const i
     flapw_status st = check_generate(h, n_k, k, n_g, g, at, rad, pot, H, S, ldh, prec, slices);
     if (st != FLAPW_OK) return st;
     hipError_t e = init_fp64_kernels();
-    if (e == hipSuccess && prec != FLAPW_PREC_FP64) e = init_split_kernels();
+    if (e == hipSuccess && prec == FLAPW_PREC_SPLIT_I8) e = init_split_kernels();
+    if (e == hipSuccess && prec == FLAPW_PREC_SPLIT_BF16) e = init_split_bf16_kernels();
     if (e == hipSuccess && h->s_method == FLAPW_S_LEGENDRE) e = init_legendre_kernels();
     if (e != hipSuccess) return dev_fail(h, e, "kernel attributes");
     flapw_plan_s *pl = new (std::nothrow) flapw_plan_s();

@@ -106,6 +106,12 @@ hipError_t launch_split_slice(const double2 *P, const double2 *Q, const double *
                               hipStream_t s);
 hipError_t launch_split_contract(const SplitProblemDev *probs, const TileDev *tiles, int n_tiles, int slices,
                                  hipStream_t s);
+// bf16 digits (split_bf16.hip): same operands, 2 bytes per digit, 8-row chunks
+hipError_t init_split_bf16_kernels();
+hipError_t launch_split_bf16_slice(const double2 *P, const double2 *Q, const double *d, long long ld, int kp2, int np,
+                                   int slices, int *eL, int *eRS, int *eRH, void *L, void *RS, void *RH, hipStream_t s);
+hipError_t launch_split_bf16_contract(const SplitProblemDev *probs, const TileDev *tiles, int n_tiles, int slices,
+                                      hipStream_t s);
 
 // Overlap matrix through the addition theorem (legendre.hip).
 //   khat : np x 4 doubles (unit K_t), ab : n_types x kLStride x np x 4 doubles {alpha, beta, ||udot||^2 beta, 0},

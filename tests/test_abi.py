@@ -155,8 +155,9 @@ def test_plan_validation(handle):
     out = ctypes.c_void_p(0x1234)
     assert handle._lib.flapw_plan_create(*_gen_args(handle, cell, n_g=0), 0, 0, ctypes.byref(out)) == -1
     assert out.value is None                                          # cleared on failure
-    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 1, 0, ctypes.byref(out)) == -6
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 1, 2, ctypes.byref(out)) == -6
     assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 2, 7, ctypes.byref(out)) == -6
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 3, 0, ctypes.byref(out)) == -1
     assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 0, 0, None) == -1
     assert handle._lib.flapw_plan_launch(None, None) == -1
     assert handle._lib.flapw_plan_destroy(None) == -1
@@ -180,7 +181,6 @@ def test_tune_validation(handle):
     assert _call_tune(handle, cell, 0.0)[0] == -1
     assert _call_tune(handle, cell, float("nan"))[0] == -1
     assert _call_tune(handle, cell, 1e-10, n_g=0)[0] == -1
-    assert _call_tune(handle, cell, 1e-10, prec=1)[0] == -6
     assert _call_tune(handle, cell, 1e-10, prec=5)[0] == -1
     bad = synthcells.config(0)
     bad.i_uu[0, 2, 3, 5] += 1e-3

@@ -133,11 +133,3 @@ def test_split_c1_sampled(ctx, oracle_lib):
 def test_split_c3_subset_sampled(ctx, oracle_lib):
     errs = _sampled(ctx, oracle_lib, synthcells.config(3, n_k=3), nsamp=32)
     assert max(errs) < TOL_SPLIT, errs
-
-
-def test_split_bf16_reports_unsupported(ctx):
-    from paper_1602_06589_amd import FlapwError
-    cell = synthcells.config(0)
-    with pytest.raises(FlapwError) as ei:
-        ctx.hs_generate(cell, cell.kpts, [_dev(cell.gvecs[0])], prec="bf16")
-    assert ei.value.status == -6

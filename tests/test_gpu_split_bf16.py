@@ -1,0 +1,121 @@
+"""GPU parity of the bf16-digit split path against the FP64 oracle.
+
+Digits hold at most 8 significant bits, so they are exact in bfloat16; products accumulate
+exactly in FP32 over 64 contraction rows and are summed in FP64.  Bar: relative Frobenius error
+<= 1e-10 per matrix with the default 6 digits; fewer digits give errors that fall by about 2^8
+per digit and stay within the truncation bound."""
+import numpy as np
+import pytest
+
+import synthcells
+
+pytestmark = pytest.mark.gpu
+
+TOL_SPLIT = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_06589_amd import Flapw
+    f = Flapw()
+    yield f
+    f.close()
+
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+
+
+def _mixed(seed=12, n_g=517, n_k=1):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, 9.0, size=(5, 3))
+    return synthcells.custom_cell("mixed", 9.0, pos, np.array([0, 1, 0, 2, 1], np.int32), [5, 3, 8], [2.0, 1.7, 1.5],
+                                  4, [n_g + 37 * i for i in range(n_k)], [seed], rotations="random")
+
+
+def _upper(M):
+    U = np.triu(M.T)
+    return U + np.triu(U, 1).conj().T
+
+
+def _relfro(got, ref):
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def _errors(ctx, oracle_lib, cell, slices=0):
+    out = ctx.hs_generate(cell, cell.kpts, [_dev(g) for g in cell.gvecs], prec="bf16", slices=slices)
+    errs = []
+    for ik, (H, S) in enumerate(out):
+        Ho, So = oracle_lib.hs_full(cell, ik)
+        errs.append((_relfro(_upper(H.cpu().numpy()), Ho), _relfro(_upper(S.cpu().numpy()), So)))
+    return errs, out
+
+
+@pytest.mark.parametrize("which", ["c0", "mixed"])
+def test_bf16_full(ctx, oracle_lib, which):
+    cell = synthcells.config(0) if which == "c0" else _mixed()
+    errs, out = _errors(ctx, oracle_lib, cell)
+    for eh, es in errs:
+        assert eh < TOL_SPLIT and es < TOL_SPLIT, (eh, es)
+    H, S = out[0]
+    assert np.all(np.diag(H.cpu().numpy()).imag == 0.0)
+    assert np.all(np.diag(S.cpu().numpy()).imag == 0.0)
+
+
+def test_bf16_digits_monotone(ctx, oracle_lib):
+    cell = _mixed(n_g=300)
+    prev = None
+    for s in (3, 4, 5, 6):
+        (eh, es), = _errors(ctx, oracle_lib, cell, slices=s)[0]
+        e = max(eh, es)
+        assert e < 2.0 ** (-8 * s + 14), (s, e)          # the truncation bound with a generous margin
+        if prev is not None:
+            assert e < prev / 16, (s, e, prev)
+        prev = e
+    assert prev < TOL_SPLIT
+
+
+def test_bf16_batched_and_legendre(ctx, oracle_lib):
+    from paper_1602_06589_amd import Flapw
+    cell = _mixed(seed=21, n_g=190, n_k=3)
+    errs, out = _errors(ctx, oracle_lib, cell)
+    for eh, es in errs:
+        assert eh < TOL_SPLIT and es < TOL_SPLIT
+    with Flapw() as f:                       # S by the addition theorem, H from bf16 digits
+        f.set_s_method("legendre")
+        out2 = f.hs_generate(cell, cell.kpts, [_dev(g) for g in cell.gvecs], prec="bf16")
+        for ik, ((H, S), (H1, _)) in enumerate(zip(out2, out)):
+            n = cell.n_g(ik)
+            up = np.triu(np.ones((n, n), bool)).T
+            assert np.array_equal(H.cpu().numpy()[up], H1.cpu().numpy()[up])
+            _, So = oracle_lib.hs_full(cell, ik)
+            assert _relfro(_upper(S.cpu().numpy()), So) < 1e-12
+
+
+def test_bf16_contract_random_operands(ctx, oracle_lib):
+    cell = _mixed(n_g=260)
+    A, B = synthcells.random_contraction_inputs([9, 9], cell.k_rows(), 260)
+    T = ctx.build_T(cell)
+    H, S = ctx.hs_contract(cell, _dev(A.T), _dev(B.T), T, prec="bf16")
+    Ho, So = oracle_lib.hs_block(cell, oracle_lib.tmat_all(cell), A, B, A, B)
+    assert _relfro(_upper(H.cpu().numpy()), Ho) < TOL_SPLIT
+    assert _relfro(_upper(S.cpu().numpy()), So) < TOL_SPLIT
+
+
+def test_bf16_c1_sampled(ctx, oracle_lib):
+    cell = synthcells.config(1)
+    out = ctx.hs_generate(cell, cell.kpts, [_dev(g) for g in cell.gvecs], prec="bf16")
+    T = oracle_lib.tmat_all(cell)
+    H, S = out[0]
+    n = cell.n_g(0)
+    rng = np.random.default_rng(200)
+    idx = np.unique(np.concatenate([rng.choice(n, 48, replace=False), [0, n - 1]]))
+    Ho, So = oracle_lib.hs_sampled(cell, 0, idx, idx, T)
+    up = idx[:, None] <= idx[None, :]
+    for M, R in ((H.cpu().numpy(), Ho), (S.cpu().numpy(), So)):
+        got = M[np.ix_(idx, idx)].T
+        assert float(np.linalg.norm((got - R)[up]) / np.linalg.norm(R[up])) < TOL_SPLIT
