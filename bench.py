@@ -2,8 +2,12 @@
 """Benchmark: H and S generation (coefficients -> T -> per-atom panels -> S/H contractions) on
 one MI355X, for the seeded synthetic workloads of synthcells.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--precs i8,fp64] [--slices s]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--precs i8,fp64,i8+leg,fp64+leg]
+                    [--slices s]
 
+A path is a precision (i8, bf16 or fp64 for the S/H contraction) with an optional "+leg": S then
+comes from the addition theorem (section 3.1) and the contraction computes H alone.  The first
+path is the headline.
 A step is one flapw_hs_generate call over every k-point of the workload (the whole path).
 Inputs (G lists) are resident in HBM before timing starts; K timed steps are bracketed by
 torch.cuda.synchronize().  Prints one JSON line:
@@ -39,7 +43,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
 
 
 def kernel_sources_sha(prec: str) -> str:
-    names = ["contract_fp64.hip", "common.hpp"] if prec == "fp64" else ["split.hip", "common.hpp"]
+    names = {"fp64": ["contract_fp64.hip"], "i8": ["split.hip"], "bf16": ["split_bf16.hip"]}[prec]
     h = hashlib.sha256()
     for n in names:
         with open(os.path.join(ROOT, "paper_1602_06589_amd", "csrc", n), "rb") as f:
@@ -102,11 +106,11 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--precs", default="i8,fp64",
+    ap.add_argument("--precs", default="i8,fp64,i8+leg,fp64+leg",
                     help="paths to measure; the first is the headline (value, roofline)")
     ap.add_argument("--slices", type=int, default=0)
     ap.add_argument("--s-method", default="gemm", choices=["gemm", "legendre"],
-                    help="S with H on the matrix cores (the paper's method) or through the addition theorem")
+                    help="S method of paths without a '+leg' suffix")
     ap.add_argument("--nk", type=int, default=0, help="use only the first nk k-points (0 = all)")
     ap.add_argument("--cpu-sample", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -147,7 +151,10 @@ def main():
     # algorithmic flops of the contraction kernel: S and H triangles, or H alone when S comes from
     # the addition theorem
     per_mat = [8.0 * kr * cell.n_g(i) * (cell.n_g(i) + 1.0) for i in range(nk)]
-    f_contract = [(2.0 if args.s_method == "gemm" else 1.0) * x for x in per_mat]
+
+    def split_path(path):
+        prec, _, suffix = path.partition("+")
+        return prec, ("legendre" if suffix == "leg" else args.s_method)
     precs = [p.strip() for p in args.precs.split(",") if p.strip()]
     stream = torch.cuda.current_stream()
     print(f"# workload {cell.name}: {cell.n_atoms} atoms, {cell.n_types} types, K={kr}, {nk} k-points, "
@@ -155,9 +162,11 @@ def main():
           f"F_alg {sum(f_alg):.3e}", flush=True)
 
     results, outs = {}, {}
-    for prec in precs:
+    for path in precs:
+        prec, s_method = split_path(path)
+        f_contract = [(2.0 if s_method == "gemm" else 1.0) * x for x in per_mat]
         with Flapw() as fl:                   # one handle per path: its work buffers are freed after
-            fl.set_s_method(args.s_method)
+            fl.set_s_method(s_method)
             out = [(torch.zeros((cell.n_g(i), cell.n_g(i)), dtype=torch.complex128, device="cuda"),
                     torch.zeros((cell.n_g(i), cell.n_g(i)), dtype=torch.complex128, device="cuda")) for i in range(nk)]
             for _ in range(args.warmup):
@@ -179,16 +188,16 @@ def main():
             fl.profile(False)
             n_l, k_ms = kern[KERNEL[prec]]
             achieved = sum(f_contract) * args.steps / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
-            results[prec] = {
-                "ms_per_step": ms, "wall_s": wall, "ms_per_kpoint": ms / nk,
+            results[path] = {
+                "s_method": s_method, "ms_per_step": ms, "wall_s": wall, "ms_per_kpoint": ms / nk,
                 "tflops": sum(f_alg) / (ms * 1e-3) / 1e12,
                 "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kern.items() if v[0]},
                 "launches_per_step": {k: v[0] // args.steps for k, v in kern.items() if v[0]},
                 "contraction_tflops": achieved,
             }
-            print(f"# {prec}: {ms:.2f} ms/step, {results[prec]['tflops']:.2f} TFLOP/s, kernels "
-                  f"{json.dumps(results[prec]['kernels_ms_per_step'])}", flush=True)
-            outs[prec] = (out[0][0], out[0][1])       # k-point 0 is what the CPU baseline samples
+            print(f"# {path}: {ms:.2f} ms/step, {results[path]['tflops']:.2f} TFLOP/s, kernels "
+                  f"{json.dumps(results[path]['kernels_ms_per_step'])}", flush=True)
+            outs[path] = (out[0][0], out[0][1])       # k-point 0 is what the CPU baseline samples
             del out
 
     base, errs = (None, {})
@@ -197,20 +206,22 @@ def main():
         for p in precs:
             results[p]["rel_err"] = errs[p]
 
-    head = precs[0]
-    r = results[head]
+    head_path = precs[0]
+    head, head_method = split_path(head_path)
+    r = results[head_path]
     n_launch = max(1, r["launches_per_step"].get(KERNEL[head], 1))
     k_ms = r["kernels_ms_per_step"].get(KERNEL[head], 0.0) / n_launch
     achieved = r["contraction_tflops"]
-    traffic = read_traffic(head, cell.name)
+    # the committed counters cover the default method (S with H on the matrix cores)
+    traffic = read_traffic(head, cell.name) if head_method == "gemm" else None
     slices = args.slices or (6 if head == "i8" else 5)
     roof = {"bound": "mfma", "kernel": KERNEL[head], "achieved": achieved, "peak": PEAKS[head],
             "unit": "TFLOP/s" if head == "fp64" else "TOP/s",
             "frac": (achieved / PEAKS[head]) if achieved else None, "traffic": traffic,
             "avg_launch_ms": k_ms, "launches_per_step": n_launch,
-            "flops_per_launch": sum(f_contract) / n_launch,
+            "flops_per_launch": sum(per_mat) * (2.0 if head_method == "gemm" else 1.0) / n_launch,
             "algorithmic_unit": ("FP64-equivalent flops of the S and H upper triangles (8 K N(N+1) each)"
-                                 if args.s_method == "gemm" else
+                                 if head_method == "gemm" else
                                  "FP64-equivalent flops of the H upper triangle (8 K N(N+1)); S by the addition theorem")}
     if head != "fp64" and achieved:
         ex = achieved * executed_per_flop(slices)
@@ -221,11 +232,11 @@ def main():
         "value": r["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "bf16": "bf16", "i8": "i8"}[head], "data": "synthetic",
-        "speedup_vs_fp64": (results["fp64"]["ms_per_step"] / r["ms_per_step"]) if "fp64" in results and head != "fp64" else None,
+        "speedup_vs_fp64": (results["fp64"]["ms_per_step"] / r["ms_per_step"]) if "fp64" in results and head_path != "fp64" else None,
         "config": {"workload": cell.name, "n_atoms": cell.n_atoms, "n_types": cell.n_types, "K": kr,
                    "lmax": int(cell.lmax.max()), "lpot": cell.lpot, "n_kpoints": nk,
                    "n_g": [cell.n_g(i) for i in range(nk)], "path": head, "slices": args.slices,
-                   "s_method": args.s_method},
+                   "s_method": head_method},
         "ms_per_kpoint": r["ms_per_kpoint"],
         "roofline": roof,
         "cpu_baseline": base,

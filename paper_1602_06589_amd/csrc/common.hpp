@@ -86,9 +86,10 @@ hipError_t launch_tmat(int n_types, const int *lmax_dev, int lstride, int lpot, 
                        const double *i_dd, const double *e_l, const double *ud_norm2, double2 *T, long long ldt,
                        hipStream_t s);
 
+// real_t: T is known to be real (built by the library from real integrals): half the MFMAs
 hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, const int *atom_type, const int *atom_nl2,
                          const long long *atom_row, int n_atoms, const double2 *P, double2 *Q, long long ldp, int np,
-                         hipStream_t s);
+                         bool real_t, hipStream_t s);
 
 // with_s = false: H alone (S tiles of the problems are not touched)
 hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_tiles, bool with_s, hipStream_t s);

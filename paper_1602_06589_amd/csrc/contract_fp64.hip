@@ -47,7 +47,8 @@ __device__ __forceinline__ v4d mfma(double a, double b, v4d c)
 // LDS panels are [column][k] complex; lane l reads row k = ks + l/16 of column base + l%16.
 // acc[y][0] = Re, acc[y][1] = Im.  The first sweep issues Xr.Yr and Xr.Yi for every block, the
 // second Xi.Yi and -Xi.Yr, so no two consecutive MFMAs use the same accumulator.
-template <int NY, int KS0 = 0, int KSTEP = 4>
+// REAL_X: X has no imaginary part (the second sweep would add zeros and is skipped).
+template <int NY, int KS0 = 0, int KSTEP = 4, bool REAL_X = false>
 __device__ __forceinline__ void stage_mma(const double2 (*X)[kSlot], const double2 (*Y0)[kSlot],
                                           const double2 (*Y1)[kSlot], int wm, int wn, int lane,
                                           v4d (&acc)[NY][2][2][2])
@@ -72,15 +73,17 @@ __device__ __forceinline__ void stage_mma(const double2 (*X)[kSlot], const doubl
                     acc[v][0][mi][ni] = mfma(x[mi].x, y[v][ni].x, acc[v][0][mi][ni]);
                     acc[v][1][mi][ni] = mfma(x[mi].x, y[v][ni].y, acc[v][1][mi][ni]);
                 }
+        if constexpr (!REAL_X) {
 #pragma unroll
-        for (int v = 0; v < NY; ++v)
+            for (int v = 0; v < NY; ++v)
 #pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
+                for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-                for (int ni = 0; ni < 2; ++ni) {
-                    acc[v][0][mi][ni] = mfma(x[mi].y, y[v][ni].y, acc[v][0][mi][ni]);
-                    acc[v][1][mi][ni] = mfma(-x[mi].y, y[v][ni].x, acc[v][1][mi][ni]);
-                }
+                    for (int ni = 0; ni < 2; ++ni) {
+                        acc[v][0][mi][ni] = mfma(x[mi].y, y[v][ni].y, acc[v][0][mi][ni]);
+                        acc[v][1][mi][ni] = mfma(-x[mi].y, y[v][ni].x, acc[v][1][mi][ni]);
+                    }
+        }
     }
 }
 
@@ -226,7 +229,10 @@ struct QSmem {
     double2 v[2][2][kTile][kSlot];          // [buffer][X = T columns, Y = P rows of the atom][column][k]
 };
 
-// grid: x = column tile, y = atom, z = row tile of the atom's 2NL rows
+// grid: x = column tile, y = atom, z = row tile of the atom's 2NL rows.
+// REAL_T: T has no imaginary part (T assembled from real radial integrals and real Gaunt
+// coefficients), so Re Q = T Re P and Im Q = T Im P take half the matrix-core work.
+template <bool REAL_T>
 __global__ __launch_bounds__(kThreads, 1) void qpanel_kernel(const double2 *__restrict__ T, long long ldt,
                                                              long long tstride, const int *__restrict__ atom_type,
                                                              const int *__restrict__ atom_nl2,
@@ -283,7 +289,7 @@ __global__ __launch_bounds__(kThreads, 1) void qpanel_kernel(const double2 *__re
     for (int kt = 0; kt < nkt; ++kt) {
         const int b = kt & 1;
         if (kt + 1 < nkt) Q_LOAD(kt + 1);
-        stage_mma<1>(sm.v[b][0], sm.v[b][1], sm.v[b][1], wm, wn, lane, acc);
+        stage_mma<1, 0, 4, REAL_T>(sm.v[b][0], sm.v[b][1], sm.v[b][1], wm, wn, lane, acc);
         if (kt + 1 < nkt) Q_STORE(b ^ 1);
         __syncthreads();
     }
@@ -331,7 +337,10 @@ hipError_t init_fp64_kernels()
         e = hipFuncSetAttribute((const void *)hs_fp64_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sizeof(HsSmem));
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)qpanel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+        e = hipFuncSetAttribute((const void *)qpanel_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sizeof(QSmem));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)qpanel_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sizeof(QSmem));
     done = e;
     return e;
@@ -350,14 +359,19 @@ hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_t
 
 hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, const int *atom_type, const int *atom_nl2,
                          const long long *atom_row, int n_atoms, const double2 *P, double2 *Q, long long ldp, int np,
-                         hipStream_t s)
+                         bool real_t, hipStream_t s)
 {
     hipError_t e = init_fp64_kernels();
     if (e != hipSuccess) return e;
     // row tiles: enough for the largest atom block (2 NL <= ldt)
     const int row_tiles = (int)((ldt + kTile - 1) / kTile);
-    hipLaunchKernelGGL(qpanel_kernel, dim3(np / kTile, n_atoms, row_tiles), dim3(kThreads), sizeof(QSmem), s, T, ldt,
-                       tstride, atom_type, atom_nl2, atom_row, P, Q, ldp);
+    const dim3 grid(np / kTile, n_atoms, row_tiles);
+    if (real_t)
+        hipLaunchKernelGGL(qpanel_kernel<true>, grid, dim3(kThreads), sizeof(QSmem), s, T, ldt, tstride, atom_type,
+                           atom_nl2, atom_row, P, Q, ldp);
+    else
+        hipLaunchKernelGGL(qpanel_kernel<false>, grid, dim3(kThreads), sizeof(QSmem), s, T, ldt, tstride, atom_type,
+                           atom_nl2, atom_row, P, Q, ldp);
     return hipGetLastError();
 }
 
