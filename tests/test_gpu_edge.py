@@ -1,0 +1,97 @@
+"""Edge cases of the whole path on the GPU, every precision and both S methods, against the
+oracle: one basis function, exactly one tile and one tile plus one column, a single atom with
+l_max and l''_max at the library caps, and the largest workload (c4_scale, k-point 0, in the
+configuration the benchmark times) on sampled entries."""
+import numpy as np
+import pytest
+
+import synthcells
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "i8": 1e-10, "bf16": 1e-10}
+
+
+@pytest.fixture(scope="module")
+def handles():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_06589_amd import Flapw
+    g, l = Flapw(), Flapw()
+    l.set_s_method("legendre")
+    yield {"gemm": g, "legendre": l}
+    g.close()
+    l.close()
+
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+
+
+def _upper(M):
+    U = np.triu(M.T)
+    return U + np.triu(U, 1).conj().T
+
+
+def _relfro(got, ref):
+    den = np.linalg.norm(ref)
+    return float(np.linalg.norm(got - ref) / den) if den > 0 else float(np.linalg.norm(got))
+
+
+def _cell(n_g, types=(0, 1, 0), lmax=(4, 6), lpot=4, seed=3, a=9.0):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, a, size=(len(types), 3))
+    rmt = [1.6 + 0.1 * i for i in range(len(lmax))]
+    return synthcells.custom_cell("edge", a, pos, np.array(types, np.int32), list(lmax), rmt, lpot, n_g, [seed],
+                                  rotations="random")
+
+
+def _check_full(handles, oracle_lib, cell, prec, method):
+    out = handles[method].hs_generate(cell, cell.kpts, [_dev(g) for g in cell.gvecs], prec=prec)
+    for ik, (H, S) in enumerate(out):
+        Ho, So = oracle_lib.hs_full(cell, ik)
+        eh = _relfro(_upper(H.cpu().numpy()), Ho)
+        es = _relfro(_upper(S.cpu().numpy()), So)
+        tol_s = 1e-12 if method == "legendre" else TOL[prec]
+        assert eh < TOL[prec] and es < tol_s, (prec, method, ik, eh, es)
+        assert np.all(np.diag(H.cpu().numpy()).imag == 0.0) and np.all(np.diag(S.cpu().numpy()).imag == 0.0)
+
+
+@pytest.mark.parametrize("method", ["gemm", "legendre"])
+@pytest.mark.parametrize("prec", ["fp64", "i8", "bf16"])
+@pytest.mark.parametrize("n_g", [1, 64, 65])
+def test_tile_edges(handles, oracle_lib, n_g, prec, method):
+    _check_full(handles, oracle_lib, _cell(n_g), prec, method)
+
+
+@pytest.mark.parametrize("method", ["gemm", "legendre"])
+@pytest.mark.parametrize("prec", ["fp64", "i8", "bf16"])
+def test_caps_single_atom(handles, oracle_lib, prec, method):
+    """One atom, l_max = 12 (2 NL = 338 rows) and l''_max = 12."""
+    cell = _cell(230, types=(0,), lmax=(12,), lpot=12, seed=8, a=7.0)
+    _check_full(handles, oracle_lib, cell, prec, method)
+
+
+def test_c4_kpoint0_sampled(handles, oracle_lib):
+    """The largest workload at full size (k-point 0: 512 atoms, K = 61952, N = 11621), the
+    launch configuration of the benchmark, on 40 sampled basis functions plus the first and last."""
+    cell = synthcells.config(4, n_k=1)
+    g = [_dev(x) for x in cell.gvecs]
+    n = cell.n_g(0)
+    rng = np.random.default_rng(77)
+    idx = np.unique(np.concatenate([rng.choice(n, 40, replace=False), [0, n - 1]]))
+    Ho, So = oracle_lib.hs_sampled(cell, 0, idx, idx, oracle_lib.tmat_all(cell))
+    up = idx[:, None] <= idx[None, :]
+    for method in ("gemm", "legendre"):
+        for prec in ("i8", "fp64"):
+            (H, S), = handles[method].hs_generate(cell, cell.kpts, g, prec=prec)
+            sub_idx = _dev(idx)
+            Hs = H[sub_idx][:, sub_idx].cpu().numpy().T      # entry (r, t) of the sample block
+            Ss = S[sub_idx][:, sub_idx].cpu().numpy().T
+            del H, S
+            for name, got, ref in (("H", Hs, Ho), ("S", Ss, So)):
+                err = float(np.linalg.norm((got - ref)[up]) / np.linalg.norm(ref[up]))
+                tol = 1e-12 if (prec == "fp64" or (name == "S" and method == "legendre")) else 1e-10
+                assert err < tol, (method, prec, name, err)
