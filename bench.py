@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--s-method", default="gemm", choices=["gemm", "legendre"],
                     help="S method of paths without a '+leg' suffix")
     ap.add_argument("--nk", type=int, default=0, help="use only the first nk k-points (0 = all)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner (digit count at 1e-10, tile band) on k-point 0 before timing")
     ap.add_argument("--cpu-sample", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -167,6 +169,12 @@ def main():
         f_contract = [(2.0 if s_method == "gemm" else 1.0) * x for x in per_mat]
         with Flapw() as fl:                   # one handle per path: its work buffers are freed after
             fl.set_s_method(s_method)
+            tuned = None
+            if args.tune:
+                t0 = time.perf_counter()
+                tuned = fl.tune(cell, cell.kpts[0], gdev[0], prec=prec, tol=1e-10)
+                tuned["seconds"] = time.perf_counter() - t0
+                print(f"# {path}: tuned {json.dumps(tuned)}", flush=True)
             out = [(torch.zeros((cell.n_g(i), cell.n_g(i)), dtype=torch.complex128, device="cuda"),
                     torch.zeros((cell.n_g(i), cell.n_g(i)), dtype=torch.complex128, device="cuda")) for i in range(nk)]
             for _ in range(args.warmup):
@@ -189,7 +197,7 @@ def main():
             n_l, k_ms = kern[KERNEL[prec]]
             achieved = sum(f_contract) * args.steps / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
             results[path] = {
-                "s_method": s_method, "ms_per_step": ms, "wall_s": wall, "ms_per_kpoint": ms / nk,
+                "s_method": s_method, "tuned": tuned, "ms_per_step": ms, "wall_s": wall, "ms_per_kpoint": ms / nk,
                 "tflops": sum(f_alg) / (ms * 1e-3) / 1e12,
                 "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kern.items() if v[0]},
                 "launches_per_step": {k: v[0] // args.steps for k, v in kern.items() if v[0]},
