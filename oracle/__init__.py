@@ -58,7 +58,7 @@ def _load():
             lib.or_wigner3j.restype = D
             lib.or_gaunt.argtypes = [I] * 6
             lib.or_gaunt.restype = D
-            lib.or_tmat.argtypes = [I, I, I, P, P, P, P, P, P, I, P, I]
+            lib.or_tmat.argtypes = [I, I, I, P, P, P, P, P, P, I, I, P, I]
             lib.or_coeffs.argtypes = [I, P, P, P, D, I, P, P, P, P, P, P, P, I, P, P, P, L]
             lib.or_hs_block.argtypes = [I, P, P, I, P, P, I, I, L, I, P, P, L, I, P, P, L, P, P]
             _lib = lib
@@ -96,8 +96,9 @@ def gaunt(l, m, lp, mp, lpp, mpp) -> float:
     return _load().or_gaunt(l, m, lp, mp, lpp, mpp)
 
 
-def tmat(cell, ty: int, literal: bool = False, ldt: int | None = None) -> np.ndarray:
-    """T of one atom type as a (2NL x 2NL) complex array (bra rows, ket columns)."""
+def tmat(cell, ty: int, literal: bool = False, ldt: int | None = None, lnonsph: int = -1) -> np.ndarray:
+    """T of one atom type as a (2NL x 2NL) complex array (bra rows, ket columns).  lnonsph >= 0:
+    the structured T of section 3.1 (non-spherical terms only for l', l <= lnonsph)."""
     lm = int(cell.lmax[ty])
     nl = (lm + 1) ** 2
     ldt = ldt or 2 * nl
@@ -107,16 +108,17 @@ def tmat(cell, ty: int, literal: bool = False, ldt: int | None = None) -> np.nda
             _c(cell.i_dd[ty], np.float64)]
     el = _c(cell.e_l[ty], np.float64)
     un = _c(cell.ud_norm2[ty], np.float64)
-    _load().or_tmat(lm, ls, int(cell.lpot), *[_p(a) for a in args], _p(el), _p(un), int(bool(literal)), _p(t), ldt)
+    _load().or_tmat(lm, ls, int(cell.lpot), *[_p(a) for a in args], _p(el), _p(un), int(bool(literal)), int(lnonsph),
+                      _p(t), ldt)
     return t[:, : 2 * nl].T.copy()
 
 
-def tmat_all(cell, literal: bool = False) -> np.ndarray:
+def tmat_all(cell, literal: bool = False, lnonsph: int = -1) -> np.ndarray:
     """All types, padded: (n_types, 2 NLmax, 2 NLmax), each type's matrix top-left."""
     nlmax = int((cell.lmax.max() + 1) ** 2)
     out = np.zeros((cell.n_types, 2 * nlmax, 2 * nlmax), dtype=np.complex128)
     for ty in range(cell.n_types):
-        t = tmat(cell, ty, literal)
+        t = tmat(cell, ty, literal, lnonsph=lnonsph)
         out[ty, : t.shape[0], : t.shape[1]] = t
     return out
 
@@ -159,9 +161,9 @@ def hs_block(cell, T, Al, Bl, Ar, Br):
     return H.T, S.T
 
 
-def hs_full(cell, ik: int, literal: bool = False):
-    """Full N x N H and S of one k-point (small problems only)."""
-    T = tmat_all(cell, literal)
+def hs_full(cell, ik: int, literal: bool = False, lnonsph: int = -1):
+    """Full N x N H and S of one k-point (small problems only); lnonsph as in tmat."""
+    T = tmat_all(cell, literal, lnonsph)
     A, B = coeffs(cell, ik)
     return hs_block(cell, T, A, B, A, B)
 

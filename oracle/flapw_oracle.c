@@ -151,12 +151,15 @@ double or_gaunt(int l, int m, int lp, int mp, int lpp, int mpp)
 /* ---------------------------------------------------------------------------------------
  * T matrices of one atom type (appendix A.2, eq. t_matrices):
  *   T^[XY]_{L',L} = sum_{L''} I^{(x,y)}_{l',l,L''} G_{L,L',L''} + diagonal spherical term.
+ * Structured T (section 3.1, Fig. Tmat_structure): with lnonsph >= 0 the non-spherical terms
+ * (l'' >= 1) are kept only where both l' and l are <= lnonsph; the spherical terms (l'' = 0 and
+ * the diagonal term) are kept for every l.  lnonsph < 0 keeps everything.
  * Output: T (2NL x 2NL, column-major, leading dimension ldt) = [[T^AA, T^AB], [T^BA, T^BB]],
  * rows = bra (L'), columns = ket (L), NL = (lmax+1)^2.  I arrays for this type are
  * [lstride][lstride][(lpot+1)^2] indexed [l'][l][L''].
  * ------------------------------------------------------------------------------------- */
 void or_tmat(int lmax, int lstride, int lpot, const double *i_uu, const double *i_ud, const double *i_du,
-             const double *i_dd, const double *e_l, const double *ud_norm2, int literal, zc *T, int ldt)
+             const double *i_dd, const double *e_l, const double *ud_norm2, int literal, int lnonsph, zc *T, int ldt)
 {
     int nl = (lmax + 1) * (lmax + 1);
     int nlp = (lpot + 1) * (lpot + 1);
@@ -170,7 +173,8 @@ void or_tmat(int lmax, int lstride, int lpot, const double *i_uu, const double *
                     for (int m = -l; m <= l; ++m) {
                         int Lp = lp * lp + lp + mp, L = l * l + l + m;
                         double s = 0.0;
-                        for (int lpp = 0; lpp <= lpot; ++lpp)
+                        const int dense = lnonsph < 0 || (lp <= lnonsph && l <= lnonsph);
+                        for (int lpp = 0; lpp <= (dense ? lpot : 0); ++lpp)
                             for (int mpp = -lpp; mpp <= lpp; ++mpp) {
                                 int Lpp = lpp * lpp + lpp + mpp;
                                 double iv = ints[blk][((size_t)lp * lstride + l) * nlp + Lpp];

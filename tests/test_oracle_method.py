@@ -318,3 +318,71 @@ def test_sampled_equals_full(oracle_lib):
     Hs, Ss = oracle_lib.hs_sampled(cell, 0, rows, cols)
     assert np.abs(Hs - H[np.ix_(rows, cols)]).max() < 1e-14 * np.abs(H).max()
     assert np.abs(Ss - S[np.ix_(rows, cols)]).max() < 1e-14 * np.abs(S).max()
+
+
+# ------------------------------------------------------------------ structured T (section 3.1)
+
+def _with_spherical_slot(cell, seed=5):
+    """Give the l'' = 0 slot nonzero values (the generator leaves it zero) with the symmetries
+    of the integrals: I^uu, I^dd symmetric in (l', l), I^du = (I^ud)^T."""
+    rng = np.random.default_rng(seed)
+    for ty in range(cell.n_types):
+        for lp in range(cell.lstride):
+            for l in range(lp, cell.lstride):
+                for arr in (cell.i_uu, cell.i_dd):
+                    v = rng.normal(0, 0.1)
+                    arr[ty, lp, l, 0] = arr[ty, l, lp, 0] = v
+                v = rng.normal(0, 0.1)
+                cell.i_ud[ty, lp, l, 0] = cell.i_du[ty, l, lp, 0] = v
+                v = rng.normal(0, 0.1)
+                cell.i_ud[ty, l, lp, 0] = cell.i_du[ty, lp, l, 0] = v
+    return cell
+
+
+def test_tmat_structured_no_cut_is_full(oracle_lib):
+    cell = _mixed()
+    for ty in range(cell.n_types):
+        full = oracle_lib.tmat(cell, ty)
+        for lns in (int(cell.lmax[ty]), 12):
+            assert np.array_equal(oracle_lib.tmat(cell, ty, lnonsph=lns), full)
+
+
+@pytest.mark.parametrize("lns", [0, 1, 2])
+def test_tmat_structured_blocks(oracle_lib, lns):
+    """Dense block l', l <= lns equal to the full T; outside it nothing but the diagonal, which
+    equals the T of the same potential with every l'' >= 1 integral removed (Fig. Tmat_structure)."""
+    cell = _with_spherical_slot(_mixed())
+    sph = _with_spherical_slot(_mixed())
+    for arr in (sph.i_uu, sph.i_ud, sph.i_du, sph.i_dd):
+        arr[..., 1:] = 0.0
+    for ty in range(cell.n_types):
+        lm = int(cell.lmax[ty])
+        nl = (lm + 1) ** 2
+        nd = (lns + 1) ** 2
+        full = oracle_lib.tmat(cell, ty)
+        st = oracle_lib.tmat(cell, ty, lnonsph=lns)
+        ts = oracle_lib.tmat(sph, ty)
+        inside = np.zeros(nl, bool)
+        inside[:nd] = True
+        inside2 = np.concatenate([inside, inside])
+        dense = inside2[:, None] & inside2[None, :]
+        assert np.array_equal(st[dense], full[dense])
+        L = np.tile(np.arange(nl), 2)
+        same_L = L[:, None] == L[None, :]
+        outside = ~dense
+        assert np.all(st[outside & ~same_L] == 0.0)
+        assert np.array_equal(st[outside & same_L], ts[outside & same_L])
+        assert np.any(full[outside & ~same_L] != 0.0)          # the cut removes something
+
+
+def test_H_structured_T_plumbing(oracle_lib):
+    """hs_full with lnonsph equals the definition evaluated with the structured T."""
+    cell = _with_spherical_slot(_mixed(n_g=70))
+    H, S = oracle_lib.hs_full(cell, 0, lnonsph=2)
+    T = oracle_lib.tmat_all(cell, lnonsph=2)
+    A, B = oracle_lib.coeffs(cell, 0)
+    H2, S2 = oracle_lib.hs_block(cell, T, A, B, A, B)
+    assert np.array_equal(H, H2) and np.array_equal(S, S2)
+    Hf, Sf = oracle_lib.hs_full(cell, 0)
+    assert np.array_equal(S, Sf)                                 # S does not involve T
+    assert np.abs(H - Hf).max() > 1e-6 * np.abs(Hf).max()
