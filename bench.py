@@ -66,7 +66,7 @@ def read_traffic(prec: str, workload: str):
     return None
 
 
-def cpu_baseline_leg(cell, outs, nsamp: int):
+def cpu_baseline_leg(cell, outs, nsamp: int, lnonsph: int = -1):
     """The oracle on a bounded sample (k-point 0: an nsamp x nsamp block of basis functions,
     H and S), timed on the host cores.  Also returns the relative Frobenius error of each GPU
     path on those entries (upper triangle)."""
@@ -77,7 +77,7 @@ def cpu_baseline_leg(cell, outs, nsamp: int):
     rng = np.random.default_rng(4242)
     idx = np.sort(rng.choice(n, min(nsamp, n), replace=False))
     t0 = time.perf_counter()
-    T = oracle.tmat_all(cell)
+    T = oracle.tmat_all(cell, lnonsph=lnonsph)
     Ho, So = oracle.hs_sampled(cell, ik, idx, idx, T)
     dt = time.perf_counter() - t0
     k = cell.k_rows()
@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--s-method", default="gemm", choices=["gemm", "legendre"],
                     help="S method of paths without a '+leg' suffix")
     ap.add_argument("--nk", type=int, default=0, help="use only the first nk k-points (0 = all)")
+    ap.add_argument("--lnonsph", type=int, default=-1,
+                    help="structured T: non-spherical terms only for l', l <= lnonsph (-1: dense T, the default)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (digit count at 1e-10, tile band) on k-point 0 before timing")
     ap.add_argument("--cpu-sample", type=int, default=384)
@@ -169,6 +171,7 @@ def main():
         f_contract = [(2.0 if s_method == "gemm" else 1.0) * x for x in per_mat]
         with Flapw() as fl:                   # one handle per path: its work buffers are freed after
             fl.set_s_method(s_method)
+            fl.set_lnonsph(args.lnonsph)
             tuned = None
             if args.tune:
                 t0 = time.perf_counter()
@@ -210,7 +213,7 @@ def main():
 
     base, errs = (None, {})
     if not args.no_cpu_baseline:
-        base, errs = cpu_baseline_leg(cell, outs, args.cpu_sample)
+        base, errs = cpu_baseline_leg(cell, outs, args.cpu_sample, args.lnonsph)
         for p in precs:
             results[p]["rel_err"] = errs[p]
 
@@ -244,7 +247,7 @@ def main():
         "config": {"workload": cell.name, "n_atoms": cell.n_atoms, "n_types": cell.n_types, "K": kr,
                    "lmax": int(cell.lmax.max()), "lpot": cell.lpot, "n_kpoints": nk,
                    "n_g": [cell.n_g(i) for i in range(nk)], "path": head, "slices": args.slices,
-                   "s_method": head_method},
+                   "s_method": head_method, "lnonsph": args.lnonsph},
         "ms_per_kpoint": r["ms_per_kpoint"],
         "roofline": roof,
         "cpu_baseline": base,

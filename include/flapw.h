@@ -185,6 +185,16 @@ flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const i
 typedef enum { FLAPW_S_GEMM = 0, FLAPW_S_LEGENDRE = 1 } flapw_s_method;
 flapw_status flapw_set_s_method(flapw_handle h, flapw_s_method method);
 
+/* Structured T (section 3.1, Fig. Tmat_structure), a handle setting: with lnonsph >= 0 the
+ * non-spherical terms (l'' >= 1) of T are kept only where both l' and l are <= lnonsph; the
+ * spherical terms (diagonal in L: E_l, E_l ||udot||^2, 1/2, 1/2 and the l'' = 0 integrals) are
+ * kept for every l.  lnonsph = -1 (default) keeps the dense T.  Affects flapw_build_T,
+ * flapw_hs_generate, flapw_plan_create and flapw_tune (flapw_hs_contract takes T as given).
+ * With FLAPW_S_LEGENDRE and lnonsph < l_max the contraction runs over the rows l <= lnonsph
+ * only and the L-diagonal remainder of H is added by the addition-theorem kernel (the same H).
+ * Errors: FLAPW_ERR_ARG unless -1 <= lnonsph <= FLAPW_LMAX_CAP. */
+flapw_status flapw_set_lnonsph(flapw_handle h, int lnonsph);
+
 /* S of one k-point through the addition theorem (FLAPW_S_LEGENDRE above), FP64.
  *   k[3] host, g device [n_g][3] Cartesian G (K_t = k + G_t), at/rad as flapw_coeffs (positions
  *   required, omega > 0).  S device, column-major, lds >= n_g; written on the upper triangle with

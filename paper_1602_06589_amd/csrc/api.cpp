@@ -132,7 +132,9 @@ struct Layout {
     long long ldE = 0;
 };
 
-void build_layout(const flapw_atoms *at, const flapw_radial *rad, bool work_layout, Layout &L)
+// lcut >= 0: the rows of each atom stop at l = min(l_max, lcut) (the dense block of a structured T
+// whose L-diagonal remainder is handled through the addition theorem); the types keep their l_max.
+void build_layout(const flapw_atoms *at, const flapw_radial *rad, bool work_layout, Layout &L, int lcut = -1)
 {
     const int na = at->n_atoms;
     L.atoms.resize(na);
@@ -157,11 +159,13 @@ void build_layout(const flapw_atoms *at, const flapw_radial *rad, bool work_layo
             r.ud_norm2 = rad->ud_norm2[q];
         }
     }
+    auto row_lmax = [&](int t) { return lcut >= 0 ? std::min(rad->lmax[t], lcut) : rad->lmax[t]; };
+    if (lcut >= 0) lm = std::min(lm, lcut);
     L.nlmax = (lm + 1) * (lm + 1);
     long long off = 0;
     for (int a = 0; a < na; ++a) {
         const int t = at->type[a];
-        const int nl = (rad->lmax[t] + 1) * (rad->lmax[t] + 1);
+        const int nl = (row_lmax(t) + 1) * (row_lmax(t) + 1);
         AtomDev &A = L.atoms[a];
         for (int i = 0; i < 3; ++i) A.pos[i] = at->pos ? at->pos[3 * a + i] : 0.0;
         for (int i = 0; i < 9; ++i) A.rot[i] = at->rot ? at->rot[9 * a + i] : (i % 4 == 0 ? 1.0 : 0.0);
@@ -200,7 +204,7 @@ void build_layout(const flapw_atoms *at, const flapw_radial *rad, bool work_layo
     }
     L.d.assign(L.kp2, 0.0);
     for (int a = 0; a < na; ++a) {
-        const int t = at->type[a], lmx = rad->lmax[t];
+        const int t = at->type[a], lmx = row_lmax(t);
         const long long r0 = L.atom_row[a];
         const int nl = L.atoms[a].nl;
         for (int l = 0; l <= lmx; ++l)
@@ -248,12 +252,15 @@ void gauss_legendre(int n, std::vector<double> &z, std::vector<double> &w)
 // Host preparation of the T build: quadrature nodes and weights, integrals, E_l, ||udot||^2,
 // l_max, and room for the Legendre table, packed into one buffer for one upload.
 struct GauntPlan {
-    int lt = 0, nq = 0, ls = 0, lpot = 0, n_types = 0;
+    int lt = 0, nq = 0, ls = 0, lpot = 0, n_types = 0, lnonsph = -1;
     size_t oz = 0, ow = 0, o1 = 0, o2 = 0, o3 = 0, o4 = 0, oe = 0, on = 0, ol = 0, oth = 0;
 };
 
-void prepare_T(const flapw_radial *rad, const flapw_potential *pot, std::vector<unsigned char> &hb, GauntPlan &gp)
+// lnonsph >= 0: structured T; lcut >= 0: each type's row blocks stop at min(l_max, lcut).
+void prepare_T(const flapw_radial *rad, const flapw_potential *pot, std::vector<unsigned char> &hb, GauntPlan &gp,
+               int lnonsph = -1, int lcut = -1)
 {
+    gp.lnonsph = lnonsph;
     int lm = 0;
     for (int t = 0; t < rad->n_types; ++t) lm = std::max(lm, rad->lmax[t]);
     gp.lt = std::max(lm, pot->lpot);
@@ -274,7 +281,10 @@ void prepare_T(const flapw_radial *rad, const flapw_potential *pot, std::vector<
     gp.o4 = put(hb, pot->i_dd, ni);
     gp.oe = put(hb, rad->e_l, (size_t)rad->n_types * gp.ls);
     gp.on = put(hb, rad->ud_norm2, (size_t)rad->n_types * gp.ls);
-    gp.ol = put(hb, rad->lmax, (size_t)rad->n_types);
+    std::vector<int> lrow(rad->lmax, rad->lmax + rad->n_types);
+    if (lcut >= 0)
+        for (int &x : lrow) x = std::min(x, lcut);
+    gp.ol = put(hb, lrow.data(), lrow.size());
     gp.oth = round_up(hb.size(), 256);
     const size_t nth = (size_t)(gp.lt + 1) * (gp.lt + 2) / 2 * gp.nq;
     hb.resize(gp.oth + nth * sizeof(double));
@@ -289,7 +299,7 @@ flapw_status launch_T(flapw_handle h, const unsigned char *base, const GauntPlan
     e = launch_tmat(gp.n_types, (const int *)(base + gp.ol), gp.ls, gp.lpot, gp.nq, (const double *)(base + gp.ow),
                     (const double *)(base + gp.oth), (const double *)(base + gp.o1), (const double *)(base + gp.o2),
                     (const double *)(base + gp.o3), (const double *)(base + gp.o4), (const double *)(base + gp.oe),
-                    (const double *)(base + gp.on), T, ldt, s);
+                    (const double *)(base + gp.on), T, ldt, gp.lnonsph, s);
     if (e != hipSuccess) return dev_fail(h, e, "T assembly kernel");
     return FLAPW_OK;
 }
@@ -299,7 +309,7 @@ flapw_status build_T_impl(flapw_handle h, const flapw_radial *rad, const flapw_p
                           hipStream_t s)
 {
     GauntPlan gp;
-    prepare_T(rad, pot, h->host_gaunt, gp);
+    prepare_T(rad, pot, h->host_gaunt, gp, h->lnonsph);
     flapw_status st = upload(h, h->gaunt, h->host_gaunt, s);
     if (st != FLAPW_OK) return st;
     return launch_T(h, (const unsigned char *)h->gaunt.p, gp, T, ldt, s);
@@ -437,6 +447,25 @@ flapw_status run_fp64(flapw_handle h, const std::vector<ProblemDev> &probs_in, c
 }
 
 
+// The T entries that are diagonal in L, per type and l: {aa, ab, ba, bb} = the spherical term
+// (E_l, E_l ||udot||^2, 1/2, 1/2 on AA, BB, AB, BA) plus the l'' = 0 integral times
+// G_{L,L,00} = Y_00 = 1 / sqrt(4 pi) (appendix A.2, eq. t_matrices).
+void spherical_t_terms(const flapw_radial *rad, const flapw_potential *pot, std::vector<double> &out)
+{
+    const int ls = rad->lstride, nlp = (pot->lpot + 1) * (pot->lpot + 1);
+    const double y00 = 1.0 / std::sqrt(4.0 * kPi);
+    out.assign((size_t)rad->n_types * kLStride * 4, 0.0);
+    for (int t = 0; t < rad->n_types; ++t)
+        for (int l = 0; l <= rad->lmax[t]; ++l) {
+            const size_t q = (size_t)t * ls + l, ii = (q * ls + l) * nlp;
+            double *o = &out[((size_t)t * kLStride + l) * 4];
+            o[0] = rad->e_l[q] + pot->i_uu[ii] * y00;
+            o[1] = 0.5 + pot->i_ud[ii] * y00;
+            o[2] = 0.5 + pot->i_du[ii] * y00;
+            o[3] = rad->e_l[q] * rad->ud_norm2[q] + pot->i_dd[ii] * y00;
+        }
+}
+
 // ----------------------------------------------------------------------------- S/H generation plans
 
 // Everything one S/H generation over n_k k-points launches.  prepare_generate validates nothing
@@ -454,6 +483,9 @@ struct GenPlan {
     bool split = false;
     bool leg = false;            // S through the addition theorem; the contraction computes H only
     bool bf16 = false;           // split digits in bf16 (else int8)
+    int lnonsph = -1;            // structured T (-1: dense T)
+    int lh0 = 1 << 20;           // the Legendre kernel adds to H the L-diagonal terms of l >= lh0
+    size_t ohsph = 0;            // per type and l: {aa, ab, ba, bb} of those terms
     double omega = 0.0;
     int sl = 0, band = 4;
     long long ldt = 0;
@@ -463,7 +495,7 @@ struct GenPlan {
     std::vector<const double *> g;
     std::vector<int> ng;
     std::vector<long long> np;
-    std::vector<flapw_z *> S;
+    std::vector<flapw_z *> S, H;
     std::vector<long long> ldh;
     std::vector<size_t> off;     // per k-point: byte offset of its P/Q (FP64) or digits (split)
     GauntPlan gp;
@@ -521,7 +553,14 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
                               int band, bool leg, GenBuffers &b, GenPlan &p, hipStream_t s, bool sync_upload)
 {
     Layout &L = p.L;
-    build_layout(at, rad, true, L);
+    p.lnonsph = h->lnonsph;
+    int lmx = 0;
+    for (int t = 0; t < rad->n_types; ++t) lmx = std::max(lmx, rad->lmax[t]);
+    // With S from the addition theorem and a structured T, the contraction covers only the dense
+    // block (rows l <= lnonsph); the L-diagonal remainder joins the Legendre kernel.
+    const int lcut = (leg && p.lnonsph >= 0 && p.lnonsph < lmx) ? p.lnonsph : -1;
+    p.lh0 = lcut >= 0 ? lcut + 1 : (1 << 20);
+    build_layout(at, rad, true, L, lcut);
     p.n_k = n_k;
     p.leg = leg;
     p.omega = at->omega;
@@ -537,6 +576,7 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     p.g.assign(g, g + n_k);
     p.ng.assign(n_g, n_g + n_k);
     p.S.assign(S, S + n_k);
+    p.H.assign(H, H + n_k);
     p.ldh.assign(ldh, ldh + n_k);
     p.np.resize(n_k);
     for (int i = 0; i < n_k; ++i) p.np[i] = round_up(n_g[i], kTile);
@@ -544,7 +584,7 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     hipError_t e = b.tmat->ensure((size_t)rad->n_types * p.ldt * p.ldt * sizeof(double2));
     if (e != hipSuccess) return dev_fail(h, e, "allocating T");
     p.T = (double2 *)b.tmat->p;
-    prepare_T(rad, pot, *b.h_gaunt, p.gp);
+    prepare_T(rad, pot, *b.h_gaunt, p.gp, p.lnonsph, lcut);
     flapw_status st = put_device(h, *b.gaunt, *b.h_gaunt, s, sync_upload);
     if (st != FLAPW_OK) return st;
     p.gaunt = (unsigned char *)b.gaunt->p;
@@ -560,6 +600,11 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     p.oapos = put(ht, L.apos.data(), L.apos.size());
     p.olrow = put(ht, L.leg_row.data(), L.leg_row.size());
     p.olrng = put(ht, L.leg_ranges.data(), L.leg_ranges.size());
+    if (lcut >= 0) {
+        std::vector<double> hs;
+        spherical_t_terms(rad, pot, hs);
+        p.ohsph = put(ht, hs.data(), hs.size());
+    }
     if ((st = put_device(h, *b.tables, ht, s, sync_upload)) != FLAPW_OK) return st;
     p.tables = (unsigned char *)b.tables->p;
 
@@ -667,9 +712,11 @@ flapw_status enqueue_s_legendre(flapw_handle h, const GenPlan &p, int i, double2
     if (e != hipSuccess) return dev_fail(h, e, "Legendre preparation kernel");
     {
         ProfScope prof(h, "s_legendre", s);
+        const bool with_h = p.lh0 < (1 << 20) && !p.H.empty();
         e = launch_s_legendre(khat, ab, E, L.ldE, (const LegTypeRange *)(p.tables + p.olrng), p.n_types,
                               (const int *)(p.desc + p.o_stiles[i]), p.n_stiles[i], (int)p.np[i], p.ng[i],
-                              4.0 * kPi / p.omega, S, lds, s);
+                              4.0 * kPi / p.omega, S, lds, with_h ? (const double *)(p.tables + p.ohsph) : nullptr,
+                              p.lh0, with_h ? (double2 *)p.H[i] : nullptr, with_h ? (long long)p.ldh[i] : 0, s);
     }
     if (e != hipSuccess) return dev_fail(h, e, "Legendre S kernel");
     return FLAPW_OK;
@@ -696,7 +743,7 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
                 ProfScope prof(h, "qpanel", s);
                 e = launch_qpanel(p.T, p.ldt, p.ldt * p.ldt, (const int *)(p.tables + p.oty),
                                   (const int *)(p.tables + p.onl), (const long long *)(p.tables + p.orow), p.n_atoms, P,
-                                  Q, L.kp2, (int)p.np[i], true, s);
+                                  Q, L.kp2, (int)p.np[i], L.kp2, true, s);
             }
             if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
             if (p.split) {
@@ -705,7 +752,6 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
                                     (int)L.kp2};
                 if ((st = slice_problem(h, pd, p.np[i], p.sl, da, p.bf16, s)) != FLAPW_OK) return st;
             }
-            if (p.leg && (st = enqueue_s_legendre(h, p, i, (double2 *)p.S[i], p.ldh[i], s)) != FLAPW_OK) return st;
         }
         hipError_t e;
         if (p.split) {
@@ -718,6 +764,9 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
                                !p.leg, s);
         }
         if (e != hipSuccess) return dev_fail(h, e, p.split ? "S/H split-precision kernel" : "S/H FP64 kernel");
+        // S (and the L-diagonal part of H beyond the dense block) once H of the batch is written
+        for (int i = bt.i0; p.leg && i < bt.i1; ++i)
+            if ((st = enqueue_s_legendre(h, p, i, (double2 *)p.S[i], p.ldh[i], s)) != FLAPW_OK) return st;
     }
     return FLAPW_OK;
 }
@@ -1088,7 +1137,7 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
     {
         ProfScope prof(h, "qpanel", s);
         e = launch_qpanel((const double2 *)T, ldt, ldt * ldt, (const int *)(base + oty), (const int *)(base + onl),
-                          (const long long *)(base + orow), at->n_atoms, P, Q, L.kp2, (int)np, false, s);
+                          (const long long *)(base + orow), at->n_atoms, P, Q, L.kp2, (int)np, L.kp2, false, s);
     }
     if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
     ProblemDev pd{P, Q, (const double *)(base + od), (double2 *)H, (double2 *)S, L.kp2, ldh, n_g, (int)L.kp2};
@@ -1129,6 +1178,14 @@ flapw_status flapw_set_s_method(flapw_handle h, flapw_s_method method)
     if (!h) return FLAPW_ERR_ARG;
     if (method != FLAPW_S_GEMM && method != FLAPW_S_LEGENDRE) return fail(h, FLAPW_ERR_ARG, "unknown S method");
     h->s_method = (int)method;
+    return FLAPW_OK;
+}
+
+flapw_status flapw_set_lnonsph(flapw_handle h, int lnonsph)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    if (lnonsph < -1 || lnonsph > FLAPW_LMAX_CAP) return fail(h, FLAPW_ERR_ARG, "lnonsph out of range");
+    h->lnonsph = lnonsph;
     return FLAPW_OK;
 }
 

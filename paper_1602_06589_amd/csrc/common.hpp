@@ -81,15 +81,18 @@ hipError_t launch_coeffs(const double kvec[3], int n_g, int n_cols, const double
                          long long zero_rows_from, long long zero_rows_to, hipStream_t s);
 
 hipError_t launch_legendre_table(int lt, int nq, const double *z, double *theta, hipStream_t s);
+// lmax_dev: l_max of each type's row blocks; lnonsph >= 0: structured T (non-spherical terms only
+// for l', l <= lnonsph)
 hipError_t launch_tmat(int n_types, const int *lmax_dev, int lstride, int lpot, int nq, const double *w,
                        const double *theta, const double *i_uu, const double *i_ud, const double *i_du,
                        const double *i_dd, const double *e_l, const double *ud_norm2, double2 *T, long long ldt,
-                       hipStream_t s);
+                       int lnonsph, hipStream_t s);
 
-// real_t: T is known to be real (built by the library from real integrals): half the MFMAs
+// Q_a = T_type(a) P_a for every atom; rows from the end of the last atom block up to kp2 are set
+// to zero.  real_t: T is known to be real (built by the library from real integrals): half the MFMAs
 hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, const int *atom_type, const int *atom_nl2,
                          const long long *atom_row, int n_atoms, const double2 *P, double2 *Q, long long ldp, int np,
-                         bool real_t, hipStream_t s);
+                         long long kp2, bool real_t, hipStream_t s);
 
 // with_s = false: H alone (S tiles of the problems are not touched)
 hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_tiles, bool with_s, hipStream_t s);
@@ -127,10 +130,13 @@ hipError_t init_legendre_kernels();
 hipError_t launch_legendre_prep(const double kvec[3], int n_g, int np, const double *g, const TypeDev *types,
                                 int n_types, const double *apos, const int *arow, int n_atoms, double *khat,
                                 double *ab, double2 *E, long long ldE, hipStream_t s);
-// tiles: n_tiles (ti, tj) pairs with ti <= tj; S written on the upper triangle, scale = 4 pi / Omega
+// tiles: n_tiles (ti, tj) pairs with ti <= tj; S written on the upper triangle, scale = 4 pi / Omega.
+// H != nullptr: also adds to H (upper triangle) the L-diagonal T terms of l >= lh0, with
+// hsph = n_types x kLStride x {aa, ab, ba, bb}.
 hipError_t launch_s_legendre(const double *khat, const double *ab, const double2 *E, long long ldE,
                              const LegTypeRange *ranges, int n_types, const int *tiles, int n_tiles, int np, int n,
-                             double scale, double2 *S, long long lds, hipStream_t s);
+                             double scale, double2 *S, long long lds, const double *hsph, int lh0, double2 *H,
+                             long long ldh, hipStream_t s);
 
 constexpr int kTile = 64;     // output tile edge (complex elements) of the contraction kernels
 constexpr int kKTile = 16;    // contraction rows per pipeline stage (FP64 kernels)

@@ -61,6 +61,7 @@ struct flapw_context {
     flapw::DevBuf sdesc;       // split precision: descriptors
     flapw::DevBuf leg;         // S through the addition theorem: Khat, radial factors, phases of one k-point
     int s_method = 0;          // flapw_s_method of flapw_hs_generate and flapw_plan_create
+    int lnonsph = -1;          // structured T (flapw_set_lnonsph); -1: dense T
     std::vector<unsigned char> host_tables, host_gaunt, host_tiles, host_sdesc;
     std::vector<long long> host_src;
     // tuning (flapw_tune): chosen digit count and tile band per (precision, padded contraction rows)

@@ -238,12 +238,21 @@ __global__ __launch_bounds__(kThreads, 1) void qpanel_kernel(const double2 *__re
                                                              const int *__restrict__ atom_nl2,
                                                              const long long *__restrict__ atom_row,
                                                              const double2 *__restrict__ P, double2 *__restrict__ Q,
-                                                             long long ldp)
+                                                             long long ldp, int n_atoms, long long kp2)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     QSmem &sm = *reinterpret_cast<QSmem *>(smem_raw);
 
     const int a = blockIdx.y;
+    if (a == n_atoms) {                                 // the padding rows of Q are zero, like P's
+        if (blockIdx.z != 0) return;
+        const long long c0 = (long long)blockIdx.x * kTile;
+        const long long pad0 = atom_row[n_atoms - 1] + atom_nl2[n_atoms - 1];
+        const long long nr = kp2 - pad0;
+        for (long long i = threadIdx.x; i < nr * kTile; i += blockDim.x)
+            Q[(c0 + i / nr) * ldp + pad0 + i % nr] = make_double2(0.0, 0.0);
+        return;
+    }
     const int m2 = atom_nl2[a];                         // 2 NL of this atom
     const int r0 = blockIdx.z * kTile;
     if (r0 >= m2) return;
@@ -359,19 +368,19 @@ hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_t
 
 hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, const int *atom_type, const int *atom_nl2,
                          const long long *atom_row, int n_atoms, const double2 *P, double2 *Q, long long ldp, int np,
-                         bool real_t, hipStream_t s)
+                         long long kp2, bool real_t, hipStream_t s)
 {
     hipError_t e = init_fp64_kernels();
     if (e != hipSuccess) return e;
     // row tiles: enough for the largest atom block (2 NL <= ldt)
     const int row_tiles = (int)((ldt + kTile - 1) / kTile);
-    const dim3 grid(np / kTile, n_atoms, row_tiles);
+    const dim3 grid(np / kTile, n_atoms + 1, row_tiles);       // y = n_atoms: zero the padding rows
     if (real_t)
         hipLaunchKernelGGL(qpanel_kernel<true>, grid, dim3(kThreads), sizeof(QSmem), s, T, ldt, tstride, atom_type,
-                           atom_nl2, atom_row, P, Q, ldp);
+                           atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2);
     else
         hipLaunchKernelGGL(qpanel_kernel<false>, grid, dim3(kThreads), sizeof(QSmem), s, T, ldt, tstride, atom_type,
-                           atom_nl2, atom_row, P, Q, ldp);
+                           atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2);
     return hipGetLastError();
 }
 

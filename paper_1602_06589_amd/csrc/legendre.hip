@@ -14,7 +14,13 @@
 //  legendre_prep_kernel : per column t: Khat_t, and per type and l the radial factors
 //                         alpha = fA sqrt(2l+1)/W, beta = fB sqrt(2l+1)/W, beta_n = ||udot||^2 beta;
 //                         and the phases E (atoms grouped by type, each group padded to 16 rows).
-//  s_legendre_kernel    : upper-triangle 64 x 64 tiles of S.
+//  s_legendre_kernel    : upper-triangle 64 x 64 tiles of S.  With WITH_H it also adds to H the
+//                         terms of the T matrices that are diagonal in L for l > lnonsph (the part
+//                         of a structured T outside its dense block, section 3.1 Fig.
+//                         Tmat_structure):  H_{t',t} += (4 pi / Omega) sum_types Phi sum_{l > lnonsph}
+//                         P_l (2l+1)/W^2 [aa fA' fA + ab fA' fB + ba fB' fA + bb fB' fB], with
+//                         aa = E_l + I^uu_{l,l,00} Y_00, bb = E_l ||udot||^2 + I^dd_{l,l,00} Y_00,
+//                         ab = 1/2 + I^{u udot}_{l,l,00} Y_00, ba = 1/2 + I^{udot u}_{l,l,00} Y_00.
 #include "common.hpp"
 
 namespace flapw {
@@ -141,16 +147,20 @@ struct SLegSmem {
     double2 e[2][2][kTile][kSlot];                // [buffer][left, right][column][k] phases
     double4 ab[2][kLStride][kTile];               // [left, right][l][column] radial factors of one type
     double4 khat[2][kTile];                       // [left, right][column]
+    double4 hc[kLStride];                         // {aa, ab, ba, bb} of one type (WITH_H)
 };
 
 // grid: one work-group per upper-triangle tile; 4 waves, each a 32 x 32 quadrant (2 x 2 blocks
 // of 16 x 16; the accumulator of block (m, n) holds rows l/16 + 4r, column l%16 in register r).
+template <bool WITH_H>
 __global__ __launch_bounds__(kThreads, 1) void s_legendre_kernel(const double4 *__restrict__ khat,
                                                                  const double4 *__restrict__ ab,
                                                                  const double2 *__restrict__ E, long long ldE,
                                                                  const LegTypeRange *__restrict__ tr, int n_types,
                                                                  const int2 *__restrict__ tiles, int np, int n,
-                                                                 double scale, double2 *__restrict__ S, long long lds)
+                                                                 double scale, double2 *__restrict__ S, long long lds,
+                                                                 const double4 *__restrict__ hsph, int lh0,
+                                                                 double2 *__restrict__ H, long long ldh)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SLegSmem &sm = *reinterpret_cast<SLegSmem *>(smem_raw);
@@ -179,13 +189,18 @@ __global__ __launch_bounds__(kThreads, 1) void s_legendre_kernel(const double4 *
             }
         }
 
-    double sre[2][2][4], sim[2][2][4];
+    double sre[2][2][4], sim[2][2][4], hre[2][2][4], him[2][2][4];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) { sre[mi][ni][r] = 0.0; sim[mi][ni][r] = 0.0; }
+            for (int r = 0; r < 4; ++r) {
+                sre[mi][ni][r] = 0.0;
+                sim[mi][ni][r] = 0.0;
+                hre[mi][ni][r] = 0.0;
+                him[mi][ni][r] = 0.0;
+            }
 
     const int lc = tid >> 2, lk = (tid & 3) * 4;          // loader: column lc, rows lk..lk+3 of a stage
     for (int ty = 0; ty < n_types; ++ty) {
@@ -197,6 +212,7 @@ __global__ __launch_bounds__(kThreads, 1) void s_legendre_kernel(const double4 *
             const int l = rem / kTile, col = rem % kTile;
             sm.ab[side][l][col] = ab[((long long)ty * kLStride + l) * np + (side ? j0 : i0) + col];
         }
+        if (WITH_H && tid < kLStride) sm.hc[tid] = hsph[ty * kLStride + tid];
         // Phi = E^H E over this type's rows, 16 rows per stage, double-buffered through registers
         v4d acc[1][2][2][2];
 #pragma unroll
@@ -262,16 +278,23 @@ __global__ __launch_bounds__(kThreads, 1) void s_legendre_kernel(const double4 *
         for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
             for (int ni = 0; ni < 2; ++ni) {
-                double pm[4], pc[4], gsum[4];
+                double pm[4], pc[4], gsum[4], hsum[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) { pm[r] = 0.0; pc[r] = 1.0; gsum[r] = 0.0; }
+                for (int r = 0; r < 4; ++r) { pm[r] = 0.0; pc[r] = 1.0; gsum[r] = 0.0; hsum[r] = 0.0; }
                 for (int l = 0; l <= rg.lmax; ++l) {
                     const double4 bc = sm.ab[1][l][wn + ni * 16 + c];
+                    const bool hl = WITH_H && l >= lh0;
+                    double4 hq = make_double4(0.0, 0.0, 0.0, 0.0);
+                    if (hl) {
+                        const double4 hc = sm.hc[l];
+                        hq = make_double4(hc.x * bc.x + hc.y * bc.y, hc.z * bc.x + hc.w * bc.y, 0.0, 0.0);
+                    }
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const double4 br = sm.ab[0][l][wm + mi * 16 + rq + 4 * r];
                         const double cl = br.x * bc.x + br.z * bc.y;      // fA fA + ||udot||^2 fB fB
                         gsum[r] += cl * pc[r];
+                        if (hl) hsum[r] += (br.x * hq.x + br.y * hq.y) * pc[r];
                         const double pn = ((2.0 * l + 1.0) * cg[mi][ni][r] * pc[r] - l * pm[r]) / (l + 1.0);
                         pm[r] = pc[r];
                         pc[r] = pn;
@@ -281,6 +304,10 @@ __global__ __launch_bounds__(kThreads, 1) void s_legendre_kernel(const double4 *
                 for (int r = 0; r < 4; ++r) {
                     sre[mi][ni][r] += gsum[r] * acc[0][0][mi][ni][r];
                     sim[mi][ni][r] += gsum[r] * acc[0][1][mi][ni][r];
+                    if (WITH_H) {
+                        hre[mi][ni][r] += hsum[r] * acc[0][0][mi][ni][r];
+                        him[mi][ni][r] += hsum[r] * acc[0][1][mi][ni][r];
+                    }
                 }
             }
     }
@@ -294,8 +321,14 @@ __global__ __launch_bounds__(kThreads, 1) void s_legendre_kernel(const double4 *
             for (int r = 0; r < 4; ++r) {
                 const long long row = i0 + wm + mi * 16 + rq + 4 * r;
                 const long long col = j0 + wn + ni * 16 + c;
-                if (row <= col && col < n)
+                if (row <= col && col < n) {
                     S[col * lds + row] = make_double2(scale * sre[mi][ni][r], row == col ? 0.0 : scale * sim[mi][ni][r]);
+                    if (WITH_H) {
+                        double2 *hp = H + col * ldh + row;
+                        const double2 hv = *hp;
+                        *hp = make_double2(hv.x + scale * hre[mi][ni][r], row == col ? 0.0 : hv.y + scale * him[mi][ni][r]);
+                    }
+                }
             }
 }
 
@@ -305,8 +338,12 @@ hipError_t init_legendre_kernels()
 {
     static hipError_t done = hipErrorNotReady;
     if (done == hipSuccess) return done;
-    done = hipFuncSetAttribute((const void *)s_legendre_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               sizeof(SLegSmem));
+    hipError_t e = hipFuncSetAttribute((const void *)s_legendre_kernel<false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, sizeof(SLegSmem));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)s_legendre_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                sizeof(SLegSmem));
+    done = e;
     return done;
 }
 
@@ -322,13 +359,19 @@ hipError_t launch_legendre_prep(const double kvec[3], int n_g, int np, const dou
 
 hipError_t launch_s_legendre(const double *khat, const double *ab, const double2 *E, long long ldE,
                              const LegTypeRange *ranges, int n_types, const int *tiles, int n_tiles, int np, int n,
-                             double scale, double2 *S, long long lds, hipStream_t s)
+                             double scale, double2 *S, long long lds, const double *hsph, int lh0, double2 *H,
+                             long long ldh, hipStream_t s)
 {
     hipError_t e = init_legendre_kernels();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(s_legendre_kernel, dim3(n_tiles), dim3(kThreads), sizeof(SLegSmem), s, (const double4 *)khat,
-                       (const double4 *)ab, E, ldE, ranges, n_types, (const int2 *)tiles, np,
-                       n, scale, S, lds);
+    if (H)
+        hipLaunchKernelGGL(s_legendre_kernel<true>, dim3(n_tiles), dim3(kThreads), sizeof(SLegSmem), s,
+                           (const double4 *)khat, (const double4 *)ab, E, ldE, ranges, n_types, (const int2 *)tiles, np,
+                           n, scale, S, lds, (const double4 *)hsph, lh0, H, ldh);
+    else
+        hipLaunchKernelGGL(s_legendre_kernel<false>, dim3(n_tiles), dim3(kThreads), sizeof(SLegSmem), s,
+                           (const double4 *)khat, (const double4 *)ab, E, ldE, ranges, n_types, (const int2 *)tiles, np,
+                           n, scale, S, lds, (const double4 *)nullptr, 0, (double2 *)nullptr, 0LL);
     return hipGetLastError();
 }
 

@@ -47,11 +47,13 @@ __device__ inline double theta_at(const double *theta, int nq, int l, int m, int
     return (m < 0 && (am & 1)) ? -v : v;        // theta_l^{-m} = (-1)^m theta_l^m
 }
 
-// one thread per (type, row, column) of the ldt x ldt matrix of a type; rows = bra
+// one thread per (type, row, column) of the ldt x ldt matrix of a type; rows = bra.
+// lmax_t: l_max of each type's row blocks.  lnonsph >= 0: structured T (section 3.1, Fig.
+// Tmat_structure): the non-spherical terms l'' >= 1 only where l' and l are both <= lnonsph.
 __global__ void tmat_kernel(int n_types, const int *lmax_t, int lstride, int lpot, int nq, const double *w,
                             const double *theta, const double *i_uu, const double *i_ud, const double *i_du,
                             const double *i_dd, const double *e_l, const double *ud_norm2, double2 *T,
-                            long long ldt)
+                            long long ldt, int lnonsph)
 {
     const long long per = ldt * ldt;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -76,7 +78,8 @@ __global__ void tmat_kernel(int n_types, const int *lmax_t, int lstride, int lpo
     int l0 = mpp < 0 ? -mpp : mpp;
     if (l0 < (lp > l ? lp - l : l - lp)) l0 = lp > l ? lp - l : l - lp;
     if ((l0 + l + lp) & 1) ++l0;
-    const int l1 = min(lpot, l + lp);
+    const bool dense = lnonsph < 0 || (lp <= lnonsph && l <= lnonsph);
+    const int l1 = dense ? min(lpot, l + lp) : 0;
     for (int lpp = l0; lpp <= l1; lpp += 2) {
         const double iv = Il[lpp * lpp + lpp + mpp];
         if (iv == 0.0) continue;
@@ -106,11 +109,11 @@ hipError_t launch_legendre_table(int lt, int nq, const double *z, double *theta,
 hipError_t launch_tmat(int n_types, const int *lmax_dev, int lstride, int lpot, int nq, const double *w,
                        const double *theta, const double *i_uu, const double *i_ud, const double *i_du,
                        const double *i_dd, const double *e_l, const double *ud_norm2, double2 *T, long long ldt,
-                       hipStream_t s)
+                       int lnonsph, hipStream_t s)
 {
     const long long n = ldt * ldt * n_types;
     hipLaunchKernelGGL(tmat_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n_types, lmax_dev, lstride, lpot,
-                       nq, w, theta, i_uu, i_ud, i_du, i_dd, e_l, ud_norm2, T, ldt);
+                       nq, w, theta, i_uu, i_ud, i_du, i_dd, e_l, ud_norm2, T, ldt, lnonsph);
     return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ _STATUS = {0: "FLAPW_OK", -1: "FLAPW_ERR_ARG", -2: "FLAPW_ERR_WRONSKIAN", -3: "F
 
 EXPORTS = ["flapw_create", "flapw_destroy", "flapw_status_string", "flapw_last_error", "flapw_workspace_bytes",
            "flapw_coeffs", "flapw_build_T", "flapw_hs_contract", "flapw_hs_generate", "flapw_set_s_method",
-           "flapw_s_legendre", "flapw_plan_create",
+           "flapw_set_lnonsph", "flapw_s_legendre", "flapw_plan_create",
            "flapw_plan_launch", "flapw_plan_destroy", "flapw_tune", "flapw_profile_enable", "flapw_profile_query"]
 
 
@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH):
         lib.flapw_hs_contract.argtypes = [P, I, P, P, P, P, L, P, L, P, P, L, I, I, P]
         lib.flapw_hs_generate.argtypes = [P, I, P, P, P, P, P, P, P, P, P, I, I, P]
         lib.flapw_set_s_method.argtypes = [P, I]
+        lib.flapw_set_lnonsph.argtypes = [P, I]
         lib.flapw_s_legendre.argtypes = [P, P, I, P, P, P, P, L, P]
         lib.flapw_plan_create.argtypes = [P, I, P, P, P, P, P, P, P, P, P, I, I, ctypes.POINTER(P)]
         lib.flapw_plan_launch.argtypes = [P, P]
@@ -244,6 +245,10 @@ class Flapw:
         """How hs_generate and plan compute S: "gemm" (with H on the matrix cores, in the chosen
         precision) or "legendre" (addition theorem, FP64; the contraction then computes H only)."""
         self._check(self._lib.flapw_set_s_method(self._h, S_METHODS.get(method, method)))
+
+    def set_lnonsph(self, lnonsph: int = -1):
+        """Structured T: non-spherical terms only for l', l <= lnonsph (-1: dense T)."""
+        self._check(self._lib.flapw_set_lnonsph(self._h, int(lnonsph)))
 
     def s_legendre(self, system, k, g, S=None, stream=None):
         """S of one k-point through the addition theorem.  g: device tensor (n_g, 3)."""
