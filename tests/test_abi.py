@@ -196,3 +196,33 @@ def test_plan_and_tune_no_device(handle):
     assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 2, 0, ctypes.byref(out)) == -5
     st, sl, band = _call_tune(handle, cell, 1e-10)
     assert st == -5 and sl == -1 and band == -1                       # outputs untouched on failure
+
+
+def test_handle_settings_validation(handle):
+    lib = handle._lib
+    assert lib.flapw_set_lnonsph(handle._h, -2) == -1
+    assert lib.flapw_set_lnonsph(handle._h, 13) == -1
+    assert lib.flapw_set_lnonsph(handle._h, -1) == 0
+    assert lib.flapw_set_lnonsph(handle._h, 12) == 0
+    assert lib.flapw_set_s_method(handle._h, 2) == -1
+    assert lib.flapw_set_s_method(handle._h, 1) == 0
+    assert lib.flapw_set_s_method(None, 0) == -1
+    assert lib.flapw_set_lnonsph(None, 0) == -1
+
+
+def test_s_legendre_validation(handle):
+    from paper_1602_06589_amd import flapw as F
+    cell = synthcells.config(0)
+    handle._keep = []
+    rad, at = handle._radial(cell), handle._atoms(cell)
+    k = np.zeros(3)
+    call = lambda n, lds, S=0x2000: handle._lib.flapw_s_legendre(handle._h, F._ptr(k), n, ctypes.c_void_p(0x1000),
+                                                                 ctypes.byref(at), ctypes.byref(rad),
+                                                                 ctypes.c_void_p(S), lds, None)
+    assert call(0, 10) == -1
+    assert call(10, 9) == -1
+    assert call(10, 10, S=0) == -1
+    cell.u[0, 1] = cell.ud[0, 1] * cell.du[0, 1] / cell.dud[0, 1]       # W = 0
+    handle._keep = []
+    rad = handle._radial(cell)
+    assert call(10, 10) == -2
