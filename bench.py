@@ -100,6 +100,19 @@ def cpu_baseline_leg(cell, outs, nsamp: int, lnonsph: int = -1):
     return base, errs
 
 
+def mfma_ceiling():
+    """Matrix-core rates on register-resident operands distributed like the library's (the
+    microbenchmark built next to the library), or None when it is not built."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1602_06589_amd", "mfma_rate")
+    if not os.path.exists(exe):
+        return None
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +127,9 @@ def main():
     ap.add_argument("--nk", type=int, default=0, help="use only the first nk k-points (0 = all)")
     ap.add_argument("--lnonsph", type=int, default=-1,
                     help="structured T: non-spherical terms only for l', l <= lnonsph (-1: dense T, the default)")
+    ap.add_argument("--mfma-ceiling", action="store_true",
+                    help="only run the matrix-core rate microbenchmark (constant and random operands) and exit")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the matrix-core rate microbenchmark")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (digit count at 1e-10, tile band) on k-point 0 before timing")
     ap.add_argument("--cpu-sample", type=int, default=384)
@@ -123,6 +139,9 @@ def main():
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters against known bytes) and exit")
     args = ap.parse_args()
 
+    if args.mfma_ceiling:
+        print(json.dumps(mfma_ceiling()))
+        return
     if args.copy_calib:
         import torch
         n = args.copy_calib * (1 << 20)
@@ -238,6 +257,15 @@ def main():
         ex = achieved * executed_per_flop(slices)
         roof.update({"executed_ops_per_flop": executed_per_flop(slices), "executed_achieved": ex,
                      "executed_frac": ex / PEAKS[head], "slices": slices})
+    ceil = None if args.no_ceiling else mfma_ceiling()
+    if ceil:
+        key = {"i8": "i8_random_TOPs", "bf16": "bf16_random_TFLOPs", "fp64": "f64_random_TFLOPs"}[head]
+        ref = roof.get("executed_achieved", achieved)
+        roof["ceiling_random_operands"] = {
+            "rates": ceil, "value": ceil[key],
+            "frac": (ref / ceil[key]) if ref else None,
+            "note": "matrix-core rate of a register-only loop on operands distributed like this path's "
+                    "(power-limited clock); context beside the published peak, which stays the roofline"}
     line = {
         "metric": "H+S gen time/k-point & TFLOP/s: split-prec vs FP64 MFMA at ≤1e-10 rel err",
         "value": r["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

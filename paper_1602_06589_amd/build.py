@@ -17,6 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libflapw_hip.so")
+MFMA_RATE = os.path.join(HERE, "mfma_rate")                  # matrix-core ceiling microbenchmark
 ARCH = "gfx950"
 
 
@@ -61,8 +62,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
+    src = os.path.join(HERE, "microbench", "mfma_rate.hip")
+    # VGPR-form MFMAs keep the register-only loops free of accumulator copies
+    r = subprocess.run([_hipcc()] + [f for f in FLAGS if f != "-fPIC"] + ["-mllvm", "-amdgpu-mfma-vgpr-form=1", src,
+                                                                          "-o", MFMA_RATE], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for mfma_rate.hip:\n" + r.stdout + r.stderr)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", MFMA_RATE)
     return LIB
 
 
