@@ -129,6 +129,7 @@ struct Layout {
     std::vector<double> apos;
     std::vector<int> leg_row;
     std::vector<LegTypeRange> leg_ranges;
+    std::vector<double> leg_un2;            // ||udot_l||^2 per type, stride kLStride
     long long ldE = 0;
 };
 
@@ -202,6 +203,9 @@ void build_layout(const flapw_atoms *at, const flapw_radial *rad, bool work_layo
         }
         L.ldE = std::max(row, kKTile);
     }
+    L.leg_un2.assign((size_t)rad->n_types * kLStride, 0.0);
+    for (int t = 0; t < rad->n_types; ++t)
+        for (int l = 0; l <= rad->lmax[t]; ++l) L.leg_un2[(size_t)t * kLStride + l] = rad->ud_norm2[t * rad->lstride + l];
     L.d.assign(L.kp2, 0.0);
     for (int a = 0; a < na; ++a) {
         const int t = at->type[a], lmx = row_lmax(t);
@@ -500,7 +504,7 @@ struct GenPlan {
     std::vector<size_t> off;     // per k-point: byte offset of its P/Q (FP64) or digits (split)
     GauntPlan gp;
     size_t oa = 0, ot = 0, od = 0, oty = 0, onl = 0, orow = 0;
-    size_t oapos = 0, olrow = 0, olrng = 0;                  // Legendre tables
+    size_t oapos = 0, olrow = 0, olrng = 0, oun2 = 0;        // Legendre tables
     std::vector<size_t> o_stiles;                            // Legendre S tiles of each k-point
     std::vector<int> n_stiles;
     std::vector<GenBatch> batches;
@@ -519,7 +523,7 @@ struct GenBuffers {
 size_t leg_bytes(const Layout &L, long long np, int n_types, size_t *o_ab, size_t *o_E)
 {
     const size_t khat = round_up(np * 32, 256);
-    const size_t ab = round_up((long long)n_types * kLStride * np * 32, 256);
+    const size_t ab = round_up((long long)n_types * kLStride * np * 16, 256);
     *o_ab = khat;
     *o_E = khat + ab;
     return khat + ab + round_up(np * L.ldE * 16, 256);
@@ -600,6 +604,7 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     p.oapos = put(ht, L.apos.data(), L.apos.size());
     p.olrow = put(ht, L.leg_row.data(), L.leg_row.size());
     p.olrng = put(ht, L.leg_ranges.data(), L.leg_ranges.size());
+    p.oun2 = put(ht, L.leg_un2.data(), L.leg_un2.size());
     if (lcut >= 0) {
         std::vector<double> hs;
         spherical_t_terms(rad, pot, hs);
@@ -715,7 +720,8 @@ flapw_status enqueue_s_legendre(flapw_handle h, const GenPlan &p, int i, double2
         const bool with_h = p.lh0 < (1 << 20) && !p.H.empty();
         e = launch_s_legendre(khat, ab, E, L.ldE, (const LegTypeRange *)(p.tables + p.olrng), p.n_types,
                               (const int *)(p.desc + p.o_stiles[i]), p.n_stiles[i], (int)p.np[i], p.ng[i],
-                              4.0 * kPi / p.omega, S, lds, with_h ? (const double *)(p.tables + p.ohsph) : nullptr,
+                              4.0 * kPi / p.omega, S, lds, (const double *)(p.tables + p.oun2),
+                              with_h ? (const double *)(p.tables + p.ohsph) : nullptr,
                               p.lh0, with_h ? (double2 *)p.H[i] : nullptr, with_h ? (long long)p.ldh[i] : 0, s);
     }
     if (e != hipSuccess) return dev_fail(h, e, "Legendre S kernel");
@@ -1220,6 +1226,7 @@ flapw_status flapw_s_legendre(flapw_handle h, const double *k, int n_g, const do
     p.oapos = put(ht, L.apos.data(), L.apos.size());
     p.olrow = put(ht, L.leg_row.data(), L.leg_row.size());
     p.olrng = put(ht, L.leg_ranges.data(), L.leg_ranges.size());
+    p.oun2 = put(ht, L.leg_un2.data(), L.leg_un2.size());
     if ((st = upload(h, h->tables, ht, s)) != FLAPW_OK) return st;
     p.tables = (unsigned char *)h->tables.p;
     std::vector<int> tl;

@@ -118,7 +118,7 @@ hipError_t launch_split_bf16_contract(const SplitProblemDev *probs, const TileDe
                                       hipStream_t s);
 
 // Overlap matrix through the addition theorem (legendre.hip).
-//   khat : np x 4 doubles (unit K_t), ab : n_types x kLStride x np x 4 doubles {alpha, beta, ||udot||^2 beta, 0},
+//   khat : np x 4 doubles (unit K_t), ab : n_types x kLStride x np x 2 doubles {alpha, beta},
 //   E    : np columns of ldE complex phases exp(i K_t.x_a), rows grouped by type.
 struct LegTypeRange {
     int row0;             // first row of the type's atoms in E
@@ -133,10 +133,11 @@ hipError_t launch_legendre_prep(const double kvec[3], int n_g, int np, const dou
 // tiles: n_tiles (ti, tj) pairs with ti <= tj; S written on the upper triangle, scale = 4 pi / Omega.
 // H != nullptr: also adds to H (upper triangle) the L-diagonal T terms of l >= lh0, with
 // hsph = n_types x kLStride x {aa, ab, ba, bb}.
+// ud_norm2: n_types x kLStride values of ||udot_l||^2.
 hipError_t launch_s_legendre(const double *khat, const double *ab, const double2 *E, long long ldE,
                              const LegTypeRange *ranges, int n_types, const int *tiles, int n_tiles, int np, int n,
-                             double scale, double2 *S, long long lds, const double *hsph, int lh0, double2 *H,
-                             long long ldh, hipStream_t s);
+                             double scale, double2 *S, long long lds, const double *ud_norm2, const double *hsph,
+                             int lh0, double2 *H, long long ldh, hipStream_t s);
 
 constexpr int kTile = 64;     // output tile edge (complex elements) of the contraction kernels
 constexpr int kKTile = 16;    // contraction rows per pipeline stage (FP64 kernels)

@@ -37,6 +37,12 @@ typedef const double2 gdouble2;
 constexpr int kThreads = 256;
 constexpr int kSlot = kKTile + 1;
 
+// Legendre recurrence coefficients (l+1) P_{l+1} = (2l+1) x P_l - l P_{l-1}, l = 0..kLStride-1
+__constant__ double kRecA[kLStride] = {1.0, 3.0 / 2, 5.0 / 3, 7.0 / 4, 9.0 / 5, 11.0 / 6, 13.0 / 7,
+                                       15.0 / 8, 17.0 / 9, 19.0 / 10, 21.0 / 11, 23.0 / 12, 25.0 / 13};
+__constant__ double kRecB[kLStride] = {0.0, 1.0 / 2, 2.0 / 3, 3.0 / 4, 4.0 / 5, 5.0 / 6, 6.0 / 7,
+                                       7.0 / 8, 8.0 / 9, 9.0 / 10, 10.0 / 11, 11.0 / 12, 12.0 / 13};
+
 // Spherical Bessel functions j_0..j_n at x; same method as the coefficient kernel.
 __device__ void bessel_all(int n, double x, double *j)
 {
@@ -91,14 +97,14 @@ __device__ void bessel_all(int n, double x, double *j)
 
 // One thread per column t (np columns; t >= n_g gets zeros).
 //   khat[t]           : unit vector of K_t (z axis for K_t = 0, where only l = 0 survives)
-//   ab[(type kLStride + l) np + t] = {alpha, beta, ||udot||^2 beta, 0}
+//   ab[(type kLStride + l) np + t] = {alpha, beta}
 //   E[t ldE + row]    : exp(i K_t.x_a) at row = type offset + rank of the atom in its type
 __global__ __launch_bounds__(kThreads) void legendre_prep_kernel(double kx, double ky, double kz, int n_g, int np,
                                                                   const double *__restrict__ g,
                                                                   const TypeDev *__restrict__ types, int n_types,
                                                                   const double *__restrict__ apos,
                                                                   const int *__restrict__ arow, int n_atoms,
-                                                                  double4 *__restrict__ khat, double4 *__restrict__ ab,
+                                                                  double4 *__restrict__ khat, double2 *__restrict__ ab,
                                                                   double2 *__restrict__ E, long long ldE)
 {
     const int t = blockIdx.x * kThreads + threadIdx.x;
@@ -116,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void legendre_prep_kernel(double kx, doub
         double j[kLStride + 1];
         bessel_all(tp.lmax + 1, kn * tp.rmt, j);
         for (int l = 0; l < kLStride; ++l) {
-            double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+            double2 v = make_double2(0.0, 0.0);
             if (t < n_g && l <= tp.lmax) {
                 const RadialDev &r = tp.rad[l];
                 const double jl = j[l];
@@ -124,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void legendre_prep_kernel(double kx, doub
                 const double w = sqrt(2.0 * l + 1.0) * r.inv_w;
                 const double fa = (r.ud * kn * djl - r.dud * jl) * w;
                 const double fb = (r.du * jl - r.u * kn * djl) * w;
-                v = make_double4(fa, fb, r.ud_norm2 * fb, 0.0);
+                v = make_double2(fa, fb);
             }
             ab[((long long)ty * kLStride + l) * np + t] = v;
         }
@@ -145,20 +151,24 @@ __device__ __forceinline__ v4d mfma(double a, double b, v4d c)
 
 struct SLegSmem {
     double2 e[2][2][kTile][kSlot];                // [buffer][left, right][column][k] phases
-    double4 ab[2][kLStride][kTile];               // [left, right][l][column] radial factors of one type
+    double2 ab[2][2][kLStride][kTile];            // [type parity][left, right][l][column] {alpha, beta}
     double4 khat[2][kTile];                       // [left, right][column]
-    double4 hc[kLStride];                         // {aa, ab, ba, bb} of one type (WITH_H)
 };
 
 // grid: one work-group per upper-triangle tile; 4 waves, each a 32 x 32 quadrant (2 x 2 blocks
 // of 16 x 16; the accumulator of block (m, n) holds rows l/16 + 4r, column l%16 in register r).
+// The phase rows of all types form one stream of 16-row stages (types are contiguous in E); at
+// the last stage of a type the Legendre sum of that type is applied to its phase product.  The
+// radial factors of the next type are copied global -> LDS (global_load_lds) while the current
+// type streams, into the other of two buffers.
 template <bool WITH_H>
 __global__ __launch_bounds__(kThreads, 1) void s_legendre_kernel(const double4 *__restrict__ khat,
-                                                                 const double4 *__restrict__ ab,
+                                                                 const double2 *__restrict__ ab,
                                                                  const double2 *__restrict__ E, long long ldE,
                                                                  const LegTypeRange *__restrict__ tr, int n_types,
                                                                  const int2 *__restrict__ tiles, int np, int n,
                                                                  double scale, double2 *__restrict__ S, long long lds,
+                                                                 const double *__restrict__ un2,
                                                                  const double4 *__restrict__ hsph, int lh0,
                                                                  double2 *__restrict__ H, long long ldh)
 {
@@ -170,11 +180,53 @@ __global__ __launch_bounds__(kThreads, 1) void s_legendre_kernel(const double4 *
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int c = lane & 15, rq = lane >> 4;
 
+    // radial factors of type ty into buffer par: one 1 KB segment (64 columns) per (side, l)
+    auto copy_ab = [&](int ty, int par, int lmax) {
+        for (int sg = wave; sg < 2 * (lmax + 1); sg += 4) {
+            const int side = sg & 1, l = sg >> 1;
+            const double2 *src = ab + ((long long)ty * kLStride + l) * np + (side ? j0 : i0) + lane;
+            __builtin_amdgcn_global_load_lds((const int __attribute__((address_space(1))) *)src,
+                                             (int __attribute__((address_space(3))) *)&sm.ab[par][side][l][0], 16, 0,
+                                             0);
+        }
+    };
+    // next type with atoms after ty (n_types if none)
+    auto next_type = [&](int ty) {
+        int q = ty + 1;
+        while (q < n_types && tr[q].rows == 0) ++q;
+        return q;
+    };
+
+    int ty = next_type(-1);
     if (tid < 2 * kTile) {
         const int side = tid / kTile, q = tid % kTile;
         sm.khat[side][q] = khat[(side ? j0 : i0) + q];
     }
+    copy_ab(ty, 0, tr[ty].lmax);
+
+    const int lc = tid >> 2, lk = (tid & 3) * 4;          // loader: column lc, rows lk..lk+3 of a stage
+    gdouble2 *gX = (gdouble2 *)E + (i0 + lc) * ldE + lk;
+    gdouble2 *gY = (gdouble2 *)E + (j0 + lc) * ldE + lk;
+    double2 x0, x1, x2, x3, y0, y1, y2, y3;
+#define SL_LOAD(st)                                                                 \
+    do {                                                                            \
+        const long long o_ = (long long)(st) * kKTile;                              \
+        x0 = gX[o_]; x1 = gX[o_ + 1]; x2 = gX[o_ + 2]; x3 = gX[o_ + 3];             \
+        y0 = gY[o_]; y1 = gY[o_ + 1]; y2 = gY[o_ + 2]; y3 = gY[o_ + 3];             \
+    } while (0)
+#define SL_STORE(b)                                                                 \
+    do {                                                                            \
+        double2 *sx_ = &sm.e[b][0][lc][lk], *sy_ = &sm.e[b][1][lc][lk];             \
+        sx_[0] = x0; sx_[1] = x1; sx_[2] = x2; sx_[3] = x3;                         \
+        sy_[0] = y0; sy_[1] = y1; sy_[2] = y2; sy_[3] = y3;                         \
+    } while (0)
+    const int first = tr[ty].row0 / kKTile;
+    int last = 0;                                        // one past the last stage
+    for (int q = 0; q < n_types; ++q) last = max(last, (tr[q].row0 + tr[q].rows) / kKTile);
+    SL_LOAD(first);
+    SL_STORE(0);
     __syncthreads();
+
     // cosines of the 16 entries of this lane: [mi][ni][r]
     double cg[2][2][4];
 #pragma unroll
@@ -201,116 +253,103 @@ __global__ __launch_bounds__(kThreads, 1) void s_legendre_kernel(const double4 *
                 hre[mi][ni][r] = 0.0;
                 him[mi][ni][r] = 0.0;
             }
+    v4d acc[2][2][2];                                    // phase product of the current type: [re, im][mi][ni]
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) acc[q][m][k] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-    const int lc = tid >> 2, lk = (tid & 3) * 4;          // loader: column lc, rows lk..lk+3 of a stage
-    for (int ty = 0; ty < n_types; ++ty) {
-        const LegTypeRange rg = tr[ty];
-        if (rg.rows == 0) continue;                      // a type without atoms adds nothing
-        __syncthreads();                                 // previous type is done with sm.ab / sm.e
-        for (int q = tid; q < 2 * (rg.lmax + 1) * kTile; q += kThreads) {
-            const int side = q / ((rg.lmax + 1) * kTile), rem = q % ((rg.lmax + 1) * kTile);
-            const int l = rem / kTile, col = rem % kTile;
-            sm.ab[side][l][col] = ab[((long long)ty * kLStride + l) * np + (side ? j0 : i0) + col];
-        }
-        if (WITH_H && tid < kLStride) sm.hc[tid] = hsph[ty * kLStride + tid];
-        // Phi = E^H E over this type's rows, 16 rows per stage, double-buffered through registers
-        v4d acc[1][2][2][2];
+    int par = 0;                                         // ab buffer of the current type
+    int type_end = (tr[ty].row0 + tr[ty].rows) / kKTile;
+    int nty = next_type(ty);
+    if (nty < n_types) copy_ab(nty, 1, tr[nty].lmax);
+    for (int st = first, b = 0; st < last; ++st, b ^= 1) {
+        if (st + 1 < last) SL_LOAD(st + 1);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int ks = 0; ks < kKTile; ks += 4) {
+            const int k = ks + rq;
+            double2 xv[2], yv[2];
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
-#pragma unroll
-                for (int k = 0; k < 2; ++k) acc[0][a][m][k] = (v4d){0.0, 0.0, 0.0, 0.0};
-        gdouble2 *gX = (gdouble2 *)E + (i0 + lc) * ldE + rg.row0 + lk;
-        gdouble2 *gY = (gdouble2 *)E + (j0 + lc) * ldE + rg.row0 + lk;
-        double2 x0, x1, x2, x3, y0, y1, y2, y3;
-        const int nst = rg.rows / kKTile;
-#define SL_LOAD(st)                                                                 \
-    do {                                                                            \
-        const int o_ = (st) * kKTile;                                               \
-        x0 = gX[o_]; x1 = gX[o_ + 1]; x2 = gX[o_ + 2]; x3 = gX[o_ + 3];             \
-        y0 = gY[o_]; y1 = gY[o_ + 1]; y2 = gY[o_ + 2]; y3 = gY[o_ + 3];             \
-    } while (0)
-#define SL_STORE(b)                                                                 \
-    do {                                                                            \
-        double2 *sx_ = &sm.e[b][0][lc][lk], *sy_ = &sm.e[b][1][lc][lk];             \
-        sx_[0] = x0; sx_[1] = x1; sx_[2] = x2; sx_[3] = x3;                         \
-        sy_[0] = y0; sy_[1] = y1; sy_[2] = y2; sy_[3] = y3;                         \
-    } while (0)
-        SL_LOAD(0);
-        SL_STORE(0);
-        __syncthreads();
-        for (int st = 0; st < nst; ++st) {
-            const int b = st & 1;
-            if (st + 1 < nst) SL_LOAD(st + 1);
-#pragma unroll
-            for (int ks = 0; ks < kKTile; ks += 4) {
-                const int k = ks + rq;
-                double2 xv[2], yv[2];
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    xv[q] = sm.e[b][0][wm + q * 16 + c][k];
-                    yv[q] = sm.e[b][1][wn + q * 16 + c][k];
-                }
-                // conj(x) y: Re = xr yr + xi yi, Im = xr yi - xi yr
-#pragma unroll
-                for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < 2; ++ni) {
-                        acc[0][0][mi][ni] = mfma(xv[mi].x, yv[ni].x, acc[0][0][mi][ni]);
-                        acc[0][1][mi][ni] = mfma(xv[mi].x, yv[ni].y, acc[0][1][mi][ni]);
-                    }
-#pragma unroll
-                for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < 2; ++ni) {
-                        acc[0][0][mi][ni] = mfma(xv[mi].y, yv[ni].y, acc[0][0][mi][ni]);
-                        acc[0][1][mi][ni] = mfma(-xv[mi].y, yv[ni].x, acc[0][1][mi][ni]);
-                    }
+            for (int q = 0; q < 2; ++q) {
+                xv[q] = sm.e[b][0][wm + q * 16 + c][k];
+                yv[q] = sm.e[b][1][wn + q * 16 + c][k];
             }
-            if (st + 1 < nst) SL_STORE(b ^ 1);
-            __syncthreads();
+            // conj(x) y: Re = xr yr + xi yi, Im = xr yi - xi yr
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni) {
+                    acc[0][mi][ni] = mfma(xv[mi].x, yv[ni].x, acc[0][mi][ni]);
+                    acc[1][mi][ni] = mfma(xv[mi].x, yv[ni].y, acc[1][mi][ni]);
+                }
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni) {
+                    acc[0][mi][ni] = mfma(xv[mi].y, yv[ni].y, acc[0][mi][ni]);
+                    acc[1][mi][ni] = mfma(-xv[mi].y, yv[ni].x, acc[1][mi][ni]);
+                }
         }
-#undef SL_LOAD
-#undef SL_STORE
-        // g_type for the 16 entries, Legendre recurrence (l+1) P_{l+1} = (2l+1) x P_l - l P_{l-1}
+        if (st + 1 == type_end) {
+            // the Legendre sum of this type, recurrence (l+1) P_{l+1} = (2l+1) x P_l - l P_{l-1}
+            const int lmax = tr[ty].lmax;
+            const double *nn = un2 + ty * kLStride;
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+            for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni) {
-                double pm[4], pc[4], gsum[4], hsum[4];
+                for (int ni = 0; ni < 2; ++ni) {
+                    double pm[4], pc[4], gsum[4], hsum[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) { pm[r] = 0.0; pc[r] = 1.0; gsum[r] = 0.0; hsum[r] = 0.0; }
-                for (int l = 0; l <= rg.lmax; ++l) {
-                    const double4 bc = sm.ab[1][l][wn + ni * 16 + c];
-                    const bool hl = WITH_H && l >= lh0;
-                    double4 hq = make_double4(0.0, 0.0, 0.0, 0.0);
-                    if (hl) {
-                        const double4 hc = sm.hc[l];
-                        hq = make_double4(hc.x * bc.x + hc.y * bc.y, hc.z * bc.x + hc.w * bc.y, 0.0, 0.0);
+                    for (int r = 0; r < 4; ++r) { pm[r] = 0.0; pc[r] = 1.0; gsum[r] = 0.0; hsum[r] = 0.0; }
+                    for (int l = 0; l <= lmax; ++l) {
+                        const double2 bc = sm.ab[par][1][l][wn + ni * 16 + c];
+                        const double nb = nn[l] * bc.y;                   // ||udot||^2 fB of the ket
+                        const double ra = kRecA[l], rb = kRecB[l];
+                        const bool hl = WITH_H && l >= lh0;
+                        double2 hq = make_double2(0.0, 0.0);
+                        if (hl) {
+                            const double4 hc = hsph[ty * kLStride + l];
+                            hq = make_double2(hc.x * bc.x + hc.y * bc.y, hc.z * bc.x + hc.w * bc.y);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const double2 br = sm.ab[par][0][l][wm + mi * 16 + rq + 4 * r];
+                            gsum[r] += (br.x * bc.x + br.y * nb) * pc[r];    // fA fA + ||udot||^2 fB fB
+                            if (hl) hsum[r] += (br.x * hq.x + br.y * hq.y) * pc[r];
+                            const double pn = ra * cg[mi][ni][r] * pc[r] - rb * pm[r];
+                            pm[r] = pc[r];
+                            pc[r] = pn;
+                        }
                     }
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const double4 br = sm.ab[0][l][wm + mi * 16 + rq + 4 * r];
-                        const double cl = br.x * bc.x + br.z * bc.y;      // fA fA + ||udot||^2 fB fB
-                        gsum[r] += cl * pc[r];
-                        if (hl) hsum[r] += (br.x * hq.x + br.y * hq.y) * pc[r];
-                        const double pn = ((2.0 * l + 1.0) * cg[mi][ni][r] * pc[r] - l * pm[r]) / (l + 1.0);
-                        pm[r] = pc[r];
-                        pc[r] = pn;
+                        sre[mi][ni][r] += gsum[r] * acc[0][mi][ni][r];
+                        sim[mi][ni][r] += gsum[r] * acc[1][mi][ni][r];
+                        if (WITH_H) {
+                            hre[mi][ni][r] += hsum[r] * acc[0][mi][ni][r];
+                            him[mi][ni][r] += hsum[r] * acc[1][mi][ni][r];
+                        }
+                        acc[0][mi][ni][r] = 0.0;
+                        acc[1][mi][ni][r] = 0.0;
                     }
                 }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    sre[mi][ni][r] += gsum[r] * acc[0][0][mi][ni][r];
-                    sim[mi][ni][r] += gsum[r] * acc[0][1][mi][ni][r];
-                    if (WITH_H) {
-                        hre[mi][ni][r] += hsum[r] * acc[0][0][mi][ni][r];
-                        him[mi][ni][r] += hsum[r] * acc[0][1][mi][ni][r];
-                    }
-                }
+            ty = nty;
+            if (ty < n_types) {
+                type_end = (tr[ty].row0 + tr[ty].rows) / kKTile;
+                par ^= 1;
+                nty = next_type(ty);
             }
+        }
+        if (st + 1 < last) SL_STORE(b ^ 1);
+        __syncthreads();                                 // also completes the radial-factor copies
+        // the buffer the finished type used is free now: start the copy of the type after next
+        if (ty < n_types && nty < n_types && st + 1 == type_end - tr[ty].rows / kKTile)
+            copy_ab(nty, par ^ 1, tr[nty].lmax);
     }
+#undef SL_LOAD
+#undef SL_STORE
 
     // epilogue: upper triangle (row <= col < n); diagonal imaginary part set to zero
 #pragma unroll
@@ -353,25 +392,25 @@ hipError_t launch_legendre_prep(const double kvec[3], int n_g, int np, const dou
 {
     hipLaunchKernelGGL(legendre_prep_kernel, dim3((np + kThreads - 1) / kThreads), dim3(kThreads), 0, s, kvec[0],
                        kvec[1], kvec[2], n_g, np, g, types, n_types, apos, arow, n_atoms, (double4 *)khat,
-                       (double4 *)ab, E, ldE);
+                       (double2 *)ab, E, ldE);
     return hipGetLastError();
 }
 
 hipError_t launch_s_legendre(const double *khat, const double *ab, const double2 *E, long long ldE,
                              const LegTypeRange *ranges, int n_types, const int *tiles, int n_tiles, int np, int n,
-                             double scale, double2 *S, long long lds, const double *hsph, int lh0, double2 *H,
-                             long long ldh, hipStream_t s)
+                             double scale, double2 *S, long long lds, const double *ud_norm2, const double *hsph,
+                             int lh0, double2 *H, long long ldh, hipStream_t s)
 {
     hipError_t e = init_legendre_kernels();
     if (e != hipSuccess) return e;
     if (H)
         hipLaunchKernelGGL(s_legendre_kernel<true>, dim3(n_tiles), dim3(kThreads), sizeof(SLegSmem), s,
-                           (const double4 *)khat, (const double4 *)ab, E, ldE, ranges, n_types, (const int2 *)tiles, np,
-                           n, scale, S, lds, (const double4 *)hsph, lh0, H, ldh);
+                           (const double4 *)khat, (const double2 *)ab, E, ldE, ranges, n_types, (const int2 *)tiles, np,
+                           n, scale, S, lds, ud_norm2, (const double4 *)hsph, lh0, H, ldh);
     else
         hipLaunchKernelGGL(s_legendre_kernel<false>, dim3(n_tiles), dim3(kThreads), sizeof(SLegSmem), s,
-                           (const double4 *)khat, (const double4 *)ab, E, ldE, ranges, n_types, (const int2 *)tiles, np,
-                           n, scale, S, lds, (const double4 *)nullptr, 0, (double2 *)nullptr, 0LL);
+                           (const double4 *)khat, (const double2 *)ab, E, ldE, ranges, n_types, (const int2 *)tiles, np,
+                           n, scale, S, lds, ud_norm2, (const double4 *)nullptr, 0, (double2 *)nullptr, 0LL);
     return hipGetLastError();
 }
 
