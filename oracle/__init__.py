@@ -61,6 +61,9 @@ def _load():
             lib.or_tmat.argtypes = [I, I, I, P, P, P, P, P, P, I, I, P, I]
             lib.or_coeffs.argtypes = [I, P, P, P, D, I, P, P, P, P, P, P, P, I, P, P, P, L]
             lib.or_hs_block.argtypes = [I, P, P, I, P, P, I, I, L, I, P, P, L, I, P, P, L, P, P]
+            lib.or_radial.argtypes = [I, D, D, P, I, D, P, P, P]
+            lib.or_radial_integral.argtypes = [I, D, D, P, P, P]
+            lib.or_radial_integral.restype = D
             _lib = lib
     return _lib
 
@@ -175,3 +178,62 @@ def hs_sampled(cell, ik: int, rows, cols, T=None):
     Al, Bl = coeffs(cell, ik, rows)
     Ar, Br = coeffs(cell, ik, cols)
     return hs_block(cell, T, Al, Bl, Ar, Br)
+
+
+# ----------------------------------------------------------------------------- radial functions
+
+def radial_mesh(n_r: int, r0: float, R: float) -> np.ndarray:
+    """r_i = r0 (R / r0)^(i / (n_r - 1)); n_r - 1 must be a multiple of 4."""
+    return r0 * (R / r0) ** (np.arange(n_r) / (n_r - 1))
+
+
+def radial(n_r: int, r0: float, R: float, v, l: int, e: float):
+    """Radial function of eq. simp_Schr and its energy derivative (Hartree units) for the spherical
+    potential v on the mesh.  Returns (P, Pd) on the even mesh points and the dict of boundary
+    values u, du, ud, dud (at R) and ud_norm2."""
+    if (n_r - 1) % 4:
+        raise ValueError("n_r - 1 must be a multiple of 4")
+    v = _c(v, np.float64)
+    ne = (n_r - 1) // 2 + 1
+    P = np.zeros(ne)
+    Pd = np.zeros(ne)
+    out = np.zeros(5)
+    _load().or_radial(n_r, float(r0), float(R), _p(v), int(l), float(e), _p(P), _p(Pd), _p(out))
+    return P, Pd, dict(zip(("u", "du", "ud", "dud", "ud_norm2"), out.tolist()))
+
+
+def radial_integral(n_r: int, r0: float, R: float, fa, v, fb) -> float:
+    """Integral over [r0, R] of fa v fb dr, all on the even mesh points (Simpson's rule in ln r)."""
+    fa, v, fb = _c(fa, np.float64), _c(v, np.float64), _c(fb, np.float64)
+    return _load().or_radial_integral(n_r, float(r0), float(R), _p(fa), _p(v), _p(fb))
+
+
+def radial_setup(n_r: int, r0, rmt, v0, e_l, lmax, vlm, lpot: int):
+    """Everything the radial data and the potential descriptors need, per type: boundary values,
+    ||udot||^2 and the four integral arrays I[type][l'][l][L''] of eq. nonsph_integrals
+    (x_{l'} v_{L''} y_l integrated, x, y in {u, udot}).
+    v0: (n_types, n_r) spherical potential; vlm: (n_types, (lpot+1)^2, n_r) non-spherical
+    components; lmax per type; lstride = max lmax + 1."""
+    nt = len(lmax)
+    ls = int(max(lmax)) + 1
+    nlp = (lpot + 1) ** 2
+    out = {k: np.zeros((nt, ls)) for k in ("u", "du", "ud", "dud", "ud_norm2")}
+    ints = {k: np.zeros((nt, ls, ls, nlp)) for k in ("i_uu", "i_ud", "i_du", "i_dd")}
+    for t in range(nt):
+        fun = {}
+        for l in range(int(lmax[t]) + 1):
+            P, Pd, b = radial(n_r, r0[t], rmt[t], v0[t], l, e_l[t][l])
+            fun[l] = (P, Pd)
+            for k, val in b.items():
+                out[k][t, l] = val
+        for L2 in range(nlp):
+            ve = np.asarray(vlm[t][L2])[::2]
+            for lp in range(int(lmax[t]) + 1):
+                for l in range(int(lmax[t]) + 1):
+                    (Pp, Pdp), (Pl, Pdl) = fun[lp], fun[l]
+                    ints["i_uu"][t, lp, l, L2] = radial_integral(n_r, r0[t], rmt[t], Pp, ve, Pl)
+                    ints["i_ud"][t, lp, l, L2] = radial_integral(n_r, r0[t], rmt[t], Pp, ve, Pdl)
+                    ints["i_du"][t, lp, l, L2] = radial_integral(n_r, r0[t], rmt[t], Pdp, ve, Pl)
+                    ints["i_dd"][t, lp, l, L2] = radial_integral(n_r, r0[t], rmt[t], Pdp, ve, Pdl)
+    out.update(ints)
+    return out

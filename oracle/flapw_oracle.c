@@ -304,3 +304,95 @@ void or_hs_block(int n_atoms, const int *type, const int *lmax_t, int lstride, c
     }
     free(off);
 }
+
+/* ---------------------------------------------------------------------------------------
+ * Radial functions (section 2.2, eq. simp_Schr) and the non-spherical radial integrals
+ * (appendix A.2, eq. nonsph_integrals), in Hartree atomic units (hbar = m = 1, so the
+ * kinetic prefactor is 1/2):
+ *     -1/2 P'' + [l(l+1) / (2 r^2) + V(r) - E] P = 0,        P = r u,
+ * and its energy derivative Pd = dP/dE:
+ *     -1/2 Pd'' + [l(l+1) / (2 r^2) + V(r) - E] Pd = P.
+ * Mesh: r_i = r0 (R / r0)^(i / (n_r - 1)), i = 0..n_r-1, with n_r - 1 a multiple of 4.
+ * In x = ln r the system for (P, D = dP/dr, Pd, Dd) reads
+ *     dP/dx = r D,   dD/dx = [l(l+1)/r + 2 r (V - E)] P,
+ *     dPd/dx = r Dd, dDd/dx = [l(l+1)/r + 2 r (V - E)] Pd - 2 r P,
+ * integrated outward by classical Runge-Kutta (4th order) with step 2h, h = ln(R/r0)/(n_r-1),
+ * so that every midpoint is a mesh point where V is given; results live on the even points.
+ * Start at r0 with the regular behaviour P = r^(l+1) (1 - Z r / (l+1)), Z = -r0 V(r0), and
+ * Pd = Dd = 0.  Integrals over [r0, R] by Simpson's rule on the even points in x (dr = r dx);
+ * the piece below r0 is of order r0^3 and is left out.
+ * Then u is normalised (integral of P^2 = 1) and udot made orthogonal to it (Pd -= <P,Pd> P).
+ * Outputs on the even points (n_e = (n_r - 1)/2 + 1 values each): P, Pd; boundary values
+ * out5 = {u(R), u'(R), udot(R), udot'(R), ||udot||^2} with u = P/r, u' = D/r - P/r^2.
+ * ------------------------------------------------------------------------------------- */
+static double simpson_even(int n_r, double r0, double R, const double *f_even)
+{
+    const int ne = (n_r - 1) / 2 + 1;
+    const double h2 = 2.0 * log(R / r0) / (n_r - 1);
+    double s = 0.0;
+    for (int j = 0; j < ne; ++j) {
+        const double r = r0 * exp(h2 * j);
+        const double w = (j == 0 || j == ne - 1) ? 1.0 : ((j & 1) ? 4.0 : 2.0);
+        s += w * f_even[j] * r;
+    }
+    return s * h2 / 3.0;
+}
+
+void or_radial(int n_r, double r0, double R, const double *v, int l, double e, double *P, double *Pd, double *out5)
+{
+    const int ne = (n_r - 1) / 2 + 1;
+    const double h = log(R / r0) / (n_r - 1);
+    const double ll = l * (l + 1.0);
+    const double z = -r0 * v[0];
+    double *D = (double *)malloc(sizeof(double) * ne), *Dd = (double *)malloc(sizeof(double) * ne);
+    P[0] = pow(r0, l + 1) * (1.0 - z * r0 / (l + 1.0));
+    D[0] = (l + 1.0) * pow(r0, l) - z * (l + 2.0) / (l + 1.0) * pow(r0, l + 1);
+    Pd[0] = 0.0;
+    Dd[0] = 0.0;
+    for (int j = 0; j + 1 < ne; ++j) {
+        /* RK4 from mesh point i = 2j (x) over 2h; midpoint i + 1, end i + 2 */
+        double y[4] = {P[j], D[j], Pd[j], Dd[j]}, k[4][4];
+        for (int s = 0; s < 4; ++s) {
+            const int i = 2 * j + (s == 0 ? 0 : (s == 3 ? 2 : 1));
+            const double r = r0 * exp(h * i);
+            const double c = ll / r + 2.0 * r * (v[i] - e);
+            double yy[4];
+            for (int q = 0; q < 4; ++q) yy[q] = y[q] + (s == 0 ? 0.0 : (s == 3 ? 2.0 * h : h)) * (s == 0 ? 0.0 : k[s - 1][q]);
+            k[s][0] = r * yy[1];
+            k[s][1] = c * yy[0];
+            k[s][2] = r * yy[3];
+            k[s][3] = c * yy[2] - 2.0 * r * yy[0];
+        }
+        P[j + 1] = y[0] + 2.0 * h / 6.0 * (k[0][0] + 2.0 * k[1][0] + 2.0 * k[2][0] + k[3][0]);
+        D[j + 1] = y[1] + 2.0 * h / 6.0 * (k[0][1] + 2.0 * k[1][1] + 2.0 * k[2][1] + k[3][1]);
+        Pd[j + 1] = y[2] + 2.0 * h / 6.0 * (k[0][2] + 2.0 * k[1][2] + 2.0 * k[2][2] + k[3][2]);
+        Dd[j + 1] = y[3] + 2.0 * h / 6.0 * (k[0][3] + 2.0 * k[1][3] + 2.0 * k[2][3] + k[3][3]);
+    }
+    double *f = (double *)malloc(sizeof(double) * ne);
+    for (int j = 0; j < ne; ++j) f[j] = P[j] * P[j];
+    const double nrm = 1.0 / sqrt(simpson_even(n_r, r0, R, f));
+    for (int j = 0; j < ne; ++j) { P[j] *= nrm; D[j] *= nrm; Pd[j] *= nrm; Dd[j] *= nrm; }
+    for (int j = 0; j < ne; ++j) f[j] = P[j] * Pd[j];
+    const double c = simpson_even(n_r, r0, R, f);
+    for (int j = 0; j < ne; ++j) { Pd[j] -= c * P[j]; Dd[j] -= c * D[j]; }
+    for (int j = 0; j < ne; ++j) f[j] = Pd[j] * Pd[j];
+    out5[4] = simpson_even(n_r, r0, R, f);
+    out5[0] = P[ne - 1] / R;
+    out5[1] = D[ne - 1] / R - P[ne - 1] / (R * R);
+    out5[2] = Pd[ne - 1] / R;
+    out5[3] = Dd[ne - 1] / R - Pd[ne - 1] / (R * R);
+    free(f);
+    free(D);
+    free(Dd);
+}
+
+/* integral over [r0, R] of fa v fb dr with all three given on the even mesh points */
+double or_radial_integral(int n_r, double r0, double R, const double *fa, const double *v_even, const double *fb)
+{
+    const int ne = (n_r - 1) / 2 + 1;
+    double *f = (double *)malloc(sizeof(double) * ne);
+    for (int j = 0; j < ne; ++j) f[j] = fa[j] * v_even[j] * fb[j];
+    const double s = simpson_even(n_r, r0, R, f);
+    free(f);
+    return s;
+}
