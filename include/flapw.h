@@ -203,6 +203,47 @@ flapw_status flapw_set_lnonsph(flapw_handle h, int lnonsph);
 flapw_status flapw_s_legendre(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
                               const flapw_radial *rad, flapw_z *S, long lds, flapw_stream stream);
 
+/* Radial functions and non-spherical radial integrals from radial meshes (section 2.2,
+ * eq. simp_Schr; appendix A.2, eq. nonsph_integrals), FP64, Hartree atomic units (the kinetic
+ * prefactor of eq. simp_Schr is 1/2).  Per type tau the mesh is logarithmic,
+ *     r_i = r0 (R / r0)^(i / (n_r - 1)),  i = 0..n_r-1,
+ * with n_r - 1 a multiple of 4.  For l = 0..lmax[tau] the library solves eq. simp_Schr for P = r u
+ * at E = e_l and its energy derivative (the same equation with right-hand side P), outward from
+ * the regular small-r form P = r^(l+1)(1 - Z r/(l+1)), Z = -r0 v_sph(r0), by fourth-order
+ * Runge-Kutta in ln r with step 2 ln(R/r0)/(n_r - 1) (the odd mesh points are the midpoints), and
+ * evaluates integrals over [r0, R] by Simpson's rule in ln r on the even points.  u is normalised
+ * (integral of u^2 r^2 = 1) and udot made orthogonal to u.
+ * Outputs are the inputs of the other calls: u, du, ud, dud, ud_norm2 as in flapw_radial, host
+ * arrays [n_types * lstride] (E_l is m->e_l), and the four tables of flapw_potential, host
+ * arrays [n_types][lstride][lstride][(lpot+1)^2], with I^{(x,y)}_{l',l,L''} = integral of
+ * x_{l'}(r) v_{L''}(r) y_l(r) r^2 dr.  Entries of l > lmax[tau] are 0.  With v_lm obeying the
+ * reality rule the tables obey the symmetries flapw_build_T checks, and udot u' - u udot' = 2/R^2
+ * up to the discretisation error.
+ * The call uploads its inputs, runs two kernels on `stream` and returns after the results are
+ * on the host (it synchronises the stream).
+ * Errors: FLAPW_ERR_ARG (NULL pointer, n_types not in 1..32, lmax not in 0..FLAPW_LMAX_CAP,
+ * lstride < max lmax + 1, lpot not in 0..FLAPW_LPOT_CAP, n_r - 1 not a multiple of 4 or n_r not
+ * in 9..FLAPW_NR_CAP, r0 not in [1e-10, R), non-finite input, or a solution that overflows);
+ * FLAPW_ERR_NOT_HERMITIAN (v_lm violates v_{(l'',-m)} = (-1)^m v_{(l'',m)} by more than 1e-12
+ * of the type's largest |v_lm|); FLAPW_ERR_NOMEM, FLAPW_ERR_DEVICE.  On error no output is
+ * written. */
+#define FLAPW_NR_CAP 16385         /* largest number of radial mesh points */
+typedef struct {
+    int n_types;
+    int lstride;
+    const int *lmax;          /* [n_types] */
+    const double *rmt;        /* [n_types] muffin-tin radius R (bohr) */
+    const double *r0;         /* [n_types] first mesh point (bohr) */
+    int n_r;                  /* mesh points per type */
+    const double *e_l;        /* [n_types * lstride] energy parameters E_l (hartree) */
+    const double *v_sph;      /* [n_types][n_r] spherical potential on the mesh (hartree) */
+    int lpot;                 /* l''_max of v_lm */
+    const double *v_lm;       /* [n_types][(lpot+1)^2][n_r] components v_{L''}(r), L'' = l''^2+l''+m'' */
+} flapw_radial_mesh;
+flapw_status flapw_radial_setup(flapw_handle h, const flapw_radial_mesh *m, double *u, double *du, double *ud,
+                                double *dud, double *ud_norm2, double *i_uu, double *i_ud, double *i_du,
+                                double *i_dd, flapw_stream stream);
+
 /* Captured generation.  flapw_plan_create validates like flapw_hs_generate, allocates device
  * buffers owned by the plan (not shared with the handle), uploads every descriptor, and records
  * the whole generation (T, and per k-point coefficients, panels, digit slicing, then the grouped

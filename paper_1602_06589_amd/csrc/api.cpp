@@ -897,6 +897,7 @@ flapw_status flapw_destroy(flapw_handle h)
     h->gaunt.release();
     h->tiles.release();
     h->leg.release();
+    h->radial.release();
     split_release(h);
     delete h;
     return FLAPW_OK;
@@ -1241,6 +1242,125 @@ flapw_status flapw_s_legendre(flapw_handle h, const double *k, int n_g, const do
     if (e != hipSuccess) return dev_fail(h, e, "allocating Legendre scratch");
     p.legbuf = (unsigned char *)h->leg.p;
     return enqueue_s_legendre(h, p, 0, (double2 *)S, lds, s);
+}
+
+namespace {
+
+flapw_status check_radial_mesh(flapw_handle h, const flapw_radial_mesh *m)
+{
+    if (!m) return fail(h, FLAPW_ERR_ARG, "radial mesh descriptor is NULL");
+    if (m->n_types < 1 || m->n_types > 32) return fail(h, FLAPW_ERR_ARG, "n_types must be in 1..32");
+    if (!m->lmax || !m->rmt || !m->r0 || !m->e_l || !m->v_sph || !m->v_lm)
+        return fail(h, FLAPW_ERR_ARG, "radial mesh array pointer is NULL");
+    if (m->n_r < 9 || m->n_r > FLAPW_NR_CAP || (m->n_r - 1) % 4 != 0)
+        return fail(h, FLAPW_ERR_ARG, "n_r must be in 9.." + std::to_string(FLAPW_NR_CAP) + " with n_r - 1 a multiple of 4");
+    if (m->lpot < 0 || m->lpot > FLAPW_LPOT_CAP)
+        return fail(h, FLAPW_ERR_ARG, "lpot out of range 0.." + std::to_string(FLAPW_LPOT_CAP));
+    int lm = 0;
+    for (int t = 0; t < m->n_types; ++t) {
+        if (m->lmax[t] < 0 || m->lmax[t] > FLAPW_LMAX_CAP)
+            return fail(h, FLAPW_ERR_ARG, "lmax out of range 0.." + std::to_string(FLAPW_LMAX_CAP));
+        if (!std::isfinite(m->rmt[t]) || !std::isfinite(m->r0[t]) || !(m->r0[t] >= 1e-10) || !(m->r0[t] < m->rmt[t]))
+            return fail(h, FLAPW_ERR_ARG, "mesh of type " + std::to_string(t) + " needs 1e-10 <= r0 < rmt");
+        lm = std::max(lm, m->lmax[t]);
+    }
+    if (m->lstride < lm + 1) return fail(h, FLAPW_ERR_ARG, "lstride < max lmax + 1");
+    for (int t = 0; t < m->n_types; ++t)
+        if (!finite_all(m->e_l + (size_t)t * m->lstride, m->lmax[t] + 1))
+            return fail(h, FLAPW_ERR_ARG, "non-finite energy parameter");
+    const int nlp = (m->lpot + 1) * (m->lpot + 1);
+    if (!finite_all(m->v_sph, (size_t)m->n_types * m->n_r) || !finite_all(m->v_lm, (size_t)m->n_types * nlp * m->n_r))
+        return fail(h, FLAPW_ERR_ARG, "non-finite potential");
+    for (int t = 0; t < m->n_types; ++t) {
+        const double *v = m->v_lm + (size_t)t * nlp * m->n_r;
+        double mx = 0.0;
+        for (size_t i = 0; i < (size_t)nlp * m->n_r; ++i) mx = std::max(mx, std::fabs(v[i]));
+        for (int lpp = 1; lpp <= m->lpot; ++lpp)
+            for (int mm = 1; mm <= lpp; ++mm) {
+                const double *vp = v + (size_t)(lpp * lpp + lpp + mm) * m->n_r;
+                const double *vm = v + (size_t)(lpp * lpp + lpp - mm) * m->n_r;
+                const double sg = (mm & 1) ? -1.0 : 1.0;
+                for (int i = 0; i < m->n_r; ++i)
+                    if (std::fabs(vm[i] - sg * vp[i]) > 1e-12 * mx)
+                        return fail(h, FLAPW_ERR_NOT_HERMITIAN, "v_lm violates v(l'',-m) = (-1)^m v(l'',m)");
+            }
+    }
+    return FLAPW_OK;
+}
+
+}  // namespace
+
+flapw_status flapw_radial_setup(flapw_handle h, const flapw_radial_mesh *m, double *u, double *du, double *ud,
+                                double *dud, double *ud_norm2, double *i_uu, double *i_ud, double *i_du,
+                                double *i_dd, flapw_stream stream)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    if (!u || !du || !ud || !dud || !ud_norm2 || !i_uu || !i_ud || !i_du || !i_dd)
+        return fail(h, FLAPW_ERR_ARG, "NULL output pointer");
+    flapw_status st = check_radial_mesh(h, m);
+    if (st != FLAPW_OK) return st;
+    if (h->device < 0) return fail(h, FLAPW_ERR_DEVICE, "no HIP device");
+    hipStream_t s = (hipStream_t)stream;
+    const int nt = m->n_types, ls = m->lstride, nr = m->n_r, nlp = (m->lpot + 1) * (m->lpot + 1);
+    // device layout: small per-type inputs, v_sph, v_lm, functions, boundary values, four tables
+    std::vector<unsigned char> &hb = h->host_tables;
+    hb.clear();
+    const size_t o_r0 = put(hb, m->r0, nt), o_rmt = put(hb, m->rmt, nt), o_lmax = put(hb, m->lmax, nt);
+    const size_t o_el = put(hb, m->e_l, (size_t)nt * ls);
+    const size_t n_small = hb.size();
+    auto align = [](size_t x) { return (size_t)round_up((long long)x, 256); };
+    const size_t o_vs = align(n_small), n_vs = sizeof(double) * nt * nr;
+    const size_t o_vl = align(o_vs + n_vs), n_vl = sizeof(double) * nt * nlp * nr;
+    const size_t o_fun = align(o_vl + n_vl), n_fun = radial_fun_bytes(nt, nr);
+    const size_t o_bnd = align(o_fun + n_fun), n_bnd = sizeof(double) * nt * kLStride * 5;
+    const size_t n_tab = sizeof(double) * nt * ls * ls * nlp;
+    const size_t o_tab = align(o_bnd + n_bnd), total = o_tab + 4 * align(n_tab);
+    hipError_t e = h->radial.ensure(total);
+    if (e != hipSuccess) return dev_fail(h, e, "allocating radial buffers");
+    unsigned char *d = (unsigned char *)h->radial.p;
+    double *tab[4];
+    for (int q = 0; q < 4; ++q) tab[q] = (double *)(d + o_tab + q * align(n_tab));
+    if ((e = hipMemcpyAsync(d, hb.data(), n_small, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d + o_vs, m->v_sph, n_vs, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d + o_vl, m->v_lm, n_vl, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemsetAsync(d + o_tab, 0, 4 * align(n_tab), s)) != hipSuccess)
+        return dev_fail(h, e, "uploading radial meshes");
+    {
+        ProfScope ps(h, "radial", s);
+        e = launch_radial(nt, nr, nlp, (const double *)(d + o_r0), (const double *)(d + o_rmt),
+                          (const int *)(d + o_lmax), (const double *)(d + o_el), ls, (const double *)(d + o_vs),
+                          (const double *)(d + o_vl), (double *)(d + o_fun), (double *)(d + o_bnd), tab[0], tab[1],
+                          tab[2], tab[3], s);
+    }
+    if (e != hipSuccess) return dev_fail(h, e, "launching radial kernels");
+    std::vector<double> bnd((size_t)nt * kLStride * 5), tabs(4 * (size_t)nt * ls * ls * nlp);
+    if ((e = hipMemcpyAsync(bnd.data(), d + o_bnd, n_bnd, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return dev_fail(h, e, "reading radial results");
+    for (int q = 0; q < 4; ++q)
+        if ((e = hipMemcpyAsync(tabs.data() + q * (n_tab / sizeof(double)), tab[q], n_tab, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess)
+            return dev_fail(h, e, "reading radial results");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return dev_fail(h, e, "radial setup");
+    for (int t = 0; t < nt; ++t)
+        if (!finite_all(bnd.data() + (size_t)t * kLStride * 5, 5 * (size_t)(m->lmax[t] + 1)))
+            return fail(h, FLAPW_ERR_ARG, "radial solution of type " + std::to_string(t) +
+                                              " is not finite (energy parameter far below the potential?)");
+    if (!finite_all(tabs.data(), tabs.size())) return fail(h, FLAPW_ERR_ARG, "radial integrals are not finite");
+    for (int t = 0; t < nt; ++t)
+        for (int l = 0; l < ls; ++l) {
+            const size_t q = (size_t)t * ls + l;
+            const double *b = bnd.data() + ((size_t)t * kLStride + l) * 5;
+            const bool used = l <= m->lmax[t];
+            u[q] = used ? b[0] : 0.0;
+            du[q] = used ? b[1] : 0.0;
+            ud[q] = used ? b[2] : 0.0;
+            dud[q] = used ? b[3] : 0.0;
+            ud_norm2[q] = used ? b[4] : 0.0;
+        }
+    const size_t nn = n_tab / sizeof(double);
+    double *outs[4] = {i_uu, i_ud, i_du, i_dd};
+    for (int q = 0; q < 4; ++q) std::memcpy(outs[q], tabs.data() + q * nn, n_tab);
+    return FLAPW_OK;
 }
 
 flapw_status flapw_plan_create(flapw_handle h, int n_k, const double *k, const int *n_g, const double *const *g,

@@ -139,6 +139,14 @@ hipError_t launch_s_legendre(const double *khat, const double *ab, const double2
                              double scale, double2 *S, long long lds, const double *ud_norm2, const double *hsph,
                              int lh0, double2 *H, long long ldh, hipStream_t s);
 
+// Radial functions and radial integrals (radial.hip).  fun: scratch of radial_fun_bytes();
+// bnd: n_types x kLStride x 5 (u, u', udot, udot', ||udot||^2); i_*: the four flapw_potential
+// tables, zero-filled by the caller.
+size_t radial_fun_bytes(int n_types, int n_r);
+hipError_t launch_radial(int n_types, int n_r, int nlp, const double *r0, const double *rmt, const int *lmax,
+                         const double *e_l, int lstride, const double *v_sph, const double *v_lm, double *fun,
+                         double *bnd, double *i_uu, double *i_ud, double *i_du, double *i_dd, hipStream_t s);
+
 constexpr int kTile = 64;     // output tile edge (complex elements) of the contraction kernels
 constexpr int kKTile = 16;    // contraction rows per pipeline stage (FP64 kernels)
 

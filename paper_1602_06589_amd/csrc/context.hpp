@@ -60,6 +60,7 @@ struct flapw_context {
     flapw::DevBuf digits;      // split precision: digit planes and column exponents
     flapw::DevBuf sdesc;       // split precision: descriptors
     flapw::DevBuf leg;         // S through the addition theorem: Khat, radial factors, phases of one k-point
+    flapw::DevBuf radial;      // radial setup: meshes, potentials, functions and integral tables
     int s_method = 0;          // flapw_s_method of flapw_hs_generate and flapw_plan_create
     int lnonsph = -1;          // structured T (flapw_set_lnonsph); -1: dense T
     std::vector<unsigned char> host_tables, host_gaunt, host_tiles, host_sdesc;

@@ -36,7 +36,8 @@ _STATUS = {0: "FLAPW_OK", -1: "FLAPW_ERR_ARG", -2: "FLAPW_ERR_WRONSKIAN", -3: "F
 EXPORTS = ["flapw_create", "flapw_destroy", "flapw_status_string", "flapw_last_error", "flapw_workspace_bytes",
            "flapw_coeffs", "flapw_build_T", "flapw_hs_contract", "flapw_hs_generate", "flapw_set_s_method",
            "flapw_set_lnonsph", "flapw_s_legendre", "flapw_plan_create",
-           "flapw_plan_launch", "flapw_plan_destroy", "flapw_tune", "flapw_profile_enable", "flapw_profile_query"]
+           "flapw_plan_launch", "flapw_plan_destroy", "flapw_tune", "flapw_profile_enable", "flapw_profile_query",
+           "flapw_radial_setup"]
 
 
 class FlapwError(RuntimeError):
@@ -49,6 +50,12 @@ class _Radial(ctypes.Structure):
     _fields_ = [("n_types", ctypes.c_int), ("lstride", ctypes.c_int), ("lmax", ctypes.c_void_p),
                 ("rmt", ctypes.c_void_p), ("u", ctypes.c_void_p), ("du", ctypes.c_void_p), ("ud", ctypes.c_void_p),
                 ("dud", ctypes.c_void_p), ("ud_norm2", ctypes.c_void_p), ("e_l", ctypes.c_void_p)]
+
+
+class _RadialMesh(ctypes.Structure):
+    _fields_ = [("n_types", ctypes.c_int), ("lstride", ctypes.c_int), ("lmax", ctypes.c_void_p),
+                ("rmt", ctypes.c_void_p), ("r0", ctypes.c_void_p), ("n_r", ctypes.c_int), ("e_l", ctypes.c_void_p),
+                ("v_sph", ctypes.c_void_p), ("lpot", ctypes.c_int), ("v_lm", ctypes.c_void_p)]
 
 
 class _Atoms(ctypes.Structure):
@@ -94,6 +101,7 @@ def load_library(path: str = LIB_PATH):
         lib.flapw_tune.argtypes = [P, P, I, P, P, P, P, I, ctypes.c_double, ctypes.POINTER(I), ctypes.POINTER(I), D, D]
         lib.flapw_profile_enable.argtypes = [P, I]
         lib.flapw_profile_query.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_double)]
+        lib.flapw_radial_setup.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
         for f in EXPORTS:
             getattr(lib, f).restype = getattr(lib, f).restype or ctypes.c_int
         _lib = lib
@@ -249,6 +257,28 @@ class Flapw:
     def set_lnonsph(self, lnonsph: int = -1):
         """Structured T: non-spherical terms only for l', l <= lnonsph (-1: dense T)."""
         self._check(self._lib.flapw_set_lnonsph(self._h, int(lnonsph)))
+
+    def radial_setup(self, n_r: int, r0, rmt, v_sph, e_l, lmax, v_lm, lpot: int, stream=None):
+        """Radial boundary data and the four non-spherical integral tables from radial meshes
+        (flapw_radial_setup).  r0, rmt: per type; v_sph: (n_types, n_r); e_l: (n_types, lstride);
+        v_lm: (n_types, (lpot+1)^2, n_r).  Returns a dict with u, du, ud, dud, ud_norm2
+        (n_types, lstride) and i_uu, i_ud, i_du, i_dd (n_types, lstride, lstride, (lpot+1)^2)."""
+        self._keep = []
+        lm, r0a, rmta, el = _i32(lmax), _f64(r0), _f64(rmt), _f64(e_l)
+        vs, vl = _f64(v_sph), _f64(v_lm)
+        nt, ls = int(lm.shape[0]), int(el.shape[1])
+        nlp = (int(lpot) + 1) ** 2
+        if el.shape != (nt, ls) or vs.shape != (nt, n_r) or vl.shape != (nt, nlp, n_r) or r0a.shape != (nt,) \
+                or rmta.shape != (nt,):
+            raise ValueError("radial_setup: array shapes do not match n_types, n_r, lpot")
+        mesh = _RadialMesh(nt, ls, _ptr(lm), _ptr(rmta), _ptr(r0a), int(n_r), _ptr(el), _ptr(vs), int(lpot), _ptr(vl))
+        out = {k: np.zeros((nt, ls)) for k in ("u", "du", "ud", "dud", "ud_norm2")}
+        out.update({k: np.zeros((nt, ls, ls, nlp)) for k in ("i_uu", "i_ud", "i_du", "i_dd")})
+        self._keep += [lm, r0a, rmta, el, vs, vl, mesh]
+        self._check(self._lib.flapw_radial_setup(
+            self._h, ctypes.byref(mesh), *[_ptr(out[k]) for k in ("u", "du", "ud", "dud", "ud_norm2", "i_uu", "i_ud",
+                                                                   "i_du", "i_dd")], _stream(stream)))
+        return out
 
     def s_legendre(self, system, k, g, S=None, stream=None):
         """S of one k-point through the addition theorem.  g: device tensor (n_g, 3)."""

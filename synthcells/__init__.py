@@ -37,7 +37,8 @@ from typing import List, Optional
 
 import numpy as np
 
-__all__ = ["Cell", "config", "custom_cell", "kset", "random_contraction_inputs", "CONFIG_NAMES"]
+__all__ = ["Cell", "config", "custom_cell", "kset", "random_contraction_inputs", "radial_meshes", "RadialMeshes",
+           "CONFIG_NAMES"]
 
 CONFIG_NAMES = ["c0_small", "c1_realistic", "c2_precision", "c3_batched", "c4_scale"]
 
@@ -293,3 +294,59 @@ def random_contraction_inputs(seed, k_rows: int, n_g: int):
     a = rng.standard_normal((k_rows, n_g)) + 1j * rng.standard_normal((k_rows, n_g))
     b = rng.standard_normal((k_rows, n_g)) + 1j * rng.standard_normal((k_rows, n_g))
     return np.asfortranarray(a), np.asfortranarray(b)
+
+
+@dataclass
+class RadialMeshes:
+    """Radial meshes and potentials of the atom types (inputs of the radial solve)."""
+    n_r: int                       # points per mesh, r_i = r0 (R/r0)^(i/(n_r-1))
+    r0: np.ndarray                 # (n_types,) first mesh point (bohr)
+    rmt: np.ndarray                # (n_types,) muffin-tin radius (bohr)
+    lmax: np.ndarray               # (n_types,) int32
+    z: np.ndarray                  # (n_types,) nuclear charge used for v_sph
+    e_l: np.ndarray                # (n_types, lstride) energy parameters (hartree)
+    v_sph: np.ndarray              # (n_types, n_r) spherical potential (hartree)
+    lpot: int
+    v_lm: np.ndarray               # (n_types, (lpot+1)^2, n_r) non-spherical components
+
+
+def radial_meshes(lmax, rmt, lpot: int, n_r: int = 1001, seed=0, lstride: Optional[int] = None,
+                  r0=None) -> RadialMeshes:
+    """Seeded synthetic muffin-tin potentials on logarithmic meshes (Hartree units).
+
+    Per type: nuclear charge Z in 3..40; r0 in [1e-6, 1e-5]; the spherical potential of a nucleus
+    inside a uniform neutralising sphere of radius R, -Z/r + Z (3R^2 - r^2)/(2R^3), plus a constant
+    in [-0.3, 0.3]; E_l in [-0.5, 1.0].  Non-spherical components for l'' >= 1:
+    v_{l'',m}(r) = a (r/R)^{l''} (1 + b r/R) with a ~ N(0, 0.2/l''), b in [-1, 1], drawn for
+    m >= 0 and mirrored by v_{l'',-m} = (-1)^m v_{l'',m} (a real potential with real components);
+    the l''=0 component is zero (it belongs to the spherical potential).  n_r - 1 must be a
+    multiple of 4 (the solve steps over two mesh intervals and Simpson's rule over pairs of steps).
+    r0, when given, replaces the drawn first mesh points (one value or one per type).
+    """
+    if (n_r - 1) % 4:
+        raise ValueError("n_r - 1 must be a multiple of 4")
+    lmax = np.asarray(lmax, dtype=np.int32)
+    rmt = np.asarray(rmt, dtype=np.float64)
+    nt = lmax.shape[0]
+    ls = int(lstride or lmax.max() + 1)
+    rng = _rng([7919, int(seed)])
+    nlp = (lpot + 1) ** 2
+    z = rng.integers(3, 41, size=nt).astype(np.float64)
+    r0 = rng.uniform(1e-6, 1e-5, size=nt) if r0 is None else np.broadcast_to(np.asarray(r0, np.float64), (nt,)).copy()
+    e_l = np.zeros((nt, ls))
+    v_sph = np.zeros((nt, n_r))
+    v_lm = np.zeros((nt, nlp, n_r))
+    for t in range(nt):
+        R = rmt[t]
+        r = r0[t] * (R / r0[t]) ** (np.arange(n_r) / (n_r - 1))
+        v_sph[t] = -z[t] / r + z[t] * (3 * R * R - r * r) / (2 * R ** 3) + rng.uniform(-0.3, 0.3)
+        e_l[t, : lmax[t] + 1] = rng.uniform(-0.5, 1.0, size=lmax[t] + 1)
+        x = r / R
+        for lpp in range(1, lpot + 1):
+            for m in range(0, lpp + 1):
+                a, b = rng.normal(0.0, 0.2 / lpp), rng.uniform(-1.0, 1.0)
+                comp = a * x ** lpp * (1.0 + b * x)
+                v_lm[t, lpp * lpp + lpp + m] = comp
+                if m:
+                    v_lm[t, lpp * lpp + lpp - m] = (-1) ** m * comp
+    return RadialMeshes(n_r, r0, rmt.copy(), lmax, z, e_l, v_sph, int(lpot), v_lm)

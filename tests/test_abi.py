@@ -226,3 +226,58 @@ def test_s_legendre_validation(handle):
     handle._keep = []
     rad = handle._radial(cell)
     assert call(10, 10) == -2
+
+
+def _mesh_args(handle, m, **over):
+    from paper_1602_06589_amd import flapw as F
+    f = dict(n_types=len(m.lmax), lstride=m.e_l.shape[1], lmax=m.lmax, rmt=m.rmt, r0=m.r0, n_r=m.n_r, e_l=m.e_l,
+             v_sph=m.v_sph, lpot=m.lpot, v_lm=m.v_lm)
+    f.update(over)
+    arrs = {k: (F._i32(v) if k == "lmax" else F._f64(v)) for k, v in f.items() if isinstance(v, np.ndarray)}
+    handle._keep = list(arrs.values())
+    mesh = F._RadialMesh(f["n_types"], f["lstride"], F._ptr(arrs["lmax"]), F._ptr(arrs["rmt"]), F._ptr(arrs["r0"]),
+                         f["n_r"], F._ptr(arrs["e_l"]), F._ptr(arrs["v_sph"]), f["lpot"], F._ptr(arrs["v_lm"]))
+    handle._keep.append(mesh)
+    nt, ls, nlp = f["n_types"], f["lstride"], (max(f["lpot"], 0) + 1) ** 2
+    outs = [np.full((max(nt, 1), ls), 7.0) for _ in range(5)] + [np.full((max(nt, 1), ls, ls, nlp), 7.0) for _ in range(4)]
+    handle._keep += outs
+    return mesh, outs
+
+
+def test_radial_setup_validation(handle):
+    from paper_1602_06589_amd import flapw as F
+    m = synthcells.radial_meshes([3, 2], [2.0, 2.3], 2, n_r=41, seed=1)
+    lib = handle._lib
+
+    def call(**over):
+        mesh, outs = _mesh_args(handle, m, **over)
+        st = lib.flapw_radial_setup(handle._h, ctypes.byref(mesh), *[F._ptr(o) for o in outs], None)
+        assert all(np.all(o == 7.0) for o in outs)          # nothing written on error
+        return st
+
+    assert lib.flapw_radial_setup(handle._h, None, *([None] * 9), None) == -1
+    assert call(n_r=43) == -1                               # n_r - 1 not a multiple of 4
+    assert call(n_r=5, v_sph=m.v_sph[:, :5], v_lm=m.v_lm[:, :, :5]) == -1
+    assert call(lstride=3) == -1                            # < max lmax + 1
+    assert call(lpot=13) == -1
+    assert call(lmax=np.array([13, 2])) == -1
+    assert call(r0=np.array([2.5, 1e-6])) == -1              # r0 >= R
+    assert call(r0=np.array([1e-11, 1e-6])) == -1
+    bad = m.v_sph.copy()
+    bad[1, 7] = np.nan
+    assert call(v_sph=bad) == -1
+    bad = m.e_l.copy()
+    bad[0, 3] = np.inf
+    assert call(e_l=bad) == -1
+    bad = m.v_lm.copy()
+    bad[0, 1, 10] += 1e-3                                   # v(1,-1) != -v(1,1)
+    assert call(v_lm=bad) == -3
+    # valid arguments: without a device the call fails with FLAPW_ERR_DEVICE, else succeeds
+    st = call() if not _has_device() else None
+    if st is not None:
+        assert st == -5
+
+
+def _has_device():
+    import torch
+    return torch.cuda.device_count() > 0
