@@ -17,6 +17,9 @@ torch.cuda.synchronize().  Prints one JSON line:
              recorded by the library on the launch stream
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload; the sampled
              entries also give the relative Frobenius error of every measured path
+  radial_setup  the step upstream of the coefficients and T: radial functions and the integral
+             tables of the workload's atom types from synthetic radial meshes (--radial-nr points),
+             GPU time per call and, beside it, the oracle's time and deviation
 """
 from __future__ import annotations
 
@@ -32,18 +35,20 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAKS = {"fp64": 78.6, "bf16": 2500.0, "i8": 5000.0}        # MI355X dense matrix-core peaks, T(FL)OP/s
+PEAKS = {"fp64": 78.6, "bf16": 2500.0, "i8": 5000.0, "i8mod": 5000.0}   # MI355X dense matrix-core peaks, T(FL)OP/s
 # int8 (or bf16) operations the split kernel executes per algorithmic FP64 flop: 8 ops per complex
 # multiply-add per digit pair (4 real products), s(s+1)/2 pairs, against 8 flops per complex
-# multiply-add in the FP64 count
-def executed_per_flop(slices: int) -> float:
-    return slices * (slices + 1) / 2.0
-KERNEL = {"fp64": "hs_fp64", "bf16": "hs_split", "i8": "hs_split"}
+# multiply-add in the FP64 count; the modular path runs one product per modulus
+def executed_per_flop(slices: int, prec: str = "i8") -> float:
+    return float(slices) if prec == "i8mod" else slices * (slices + 1) / 2.0
+KERNEL = {"fp64": "hs_fp64", "bf16": "hs_split", "i8": "hs_split", "i8mod": "hs_mod"}
+DEFAULT_SLICES = {"i8": 6, "bf16": 6, "i8mod": 11}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
 
 
 def kernel_sources_sha(prec: str) -> str:
-    names = {"fp64": ["contract_fp64.hip"], "i8": ["split.hip"], "bf16": ["split_bf16.hip"]}[prec]
+    names = {"fp64": ["contract_fp64.hip"], "i8": ["split.hip"], "bf16": ["split_bf16.hip"],
+             "i8mod": ["split_mod.hip"]}[prec]
     h = hashlib.sha256()
     for n in names:
         with open(os.path.join(ROOT, "paper_1602_06589_amd", "csrc", n), "rb") as f:
@@ -100,6 +105,36 @@ def cpu_baseline_leg(cell, outs, nsamp: int, lnonsph: int = -1):
     return base, errs
 
 
+def radial_leg(cell, n_r: int, steps: int, with_oracle: bool):
+    """Radial functions and the four integral tables of the workload's atom types from synthetic
+    meshes (one flapw_radial_setup call: upload, two kernels, download), timed on the GPU; with
+    with_oracle also the oracle's time for the same call and the largest deviation from it."""
+    import synthcells
+    from paper_1602_06589_amd import Flapw
+    m = synthcells.radial_meshes(cell.lmax, cell.rmt, cell.lpot, n_r=n_r, seed=0)
+    with Flapw() as fl:
+        got = fl.radial_setup(m.n_r, m.r0, m.rmt, m.v_sph, m.e_l, m.lmax, m.v_lm, m.lpot)
+        fl.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(max(1, steps)):
+            got = fl.radial_setup(m.n_r, m.r0, m.rmt, m.v_sph, m.e_l, m.lmax, m.v_lm, m.lpot)
+        call_ms = (time.perf_counter() - t0) * 1e3 / max(1, steps)
+        n_l, k_ms = fl.kernel_time("radial")
+        fl.profile(False)
+    res = {"n_types": int(len(m.lmax)), "lmax": int(m.lmax.max()), "lpot": m.lpot, "n_r": n_r,
+           "ms_per_call": call_ms, "kernels_ms_per_call": k_ms / max(1, n_l)}
+    if with_oracle:
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.radial_setup(m.n_r, m.r0, m.rmt, m.v_sph, m.e_l, m.lmax, m.v_lm, m.lpot)
+        res["oracle_s"] = time.perf_counter() - t0
+        res["max_err_rel_to_array_max"] = max(
+            float(np.max(np.abs(got[k] - ref[k])) / np.max(np.abs(ref[k])))
+            for k in ("u", "du", "ud", "dud", "ud_norm2", "i_uu", "i_ud", "i_du", "i_dd"))
+    print(f"# radial setup: {json.dumps(res)}", flush=True)
+    return res
+
+
 def mfma_ceiling():
     """Matrix-core rates on register-resident operands distributed like the library's (the
     microbenchmark built next to the library), or None when it is not built."""
@@ -133,6 +168,9 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (digit count at 1e-10, tile band) on k-point 0 before timing")
     ap.add_argument("--cpu-sample", type=int, default=384)
+    ap.add_argument("--radial-nr", type=int, default=1001,
+                    help="mesh points of the radial-setup leg (radial functions and integrals of the "
+                         "workload's atom types); 0 skips the leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (calibrates the "
@@ -214,7 +252,8 @@ def main():
             wall = time.perf_counter() - t0
             ms = e0.elapsed_time(e1) / args.steps
             kern = {fam: fl.kernel_time(fam)
-                    for fam in ("coeffs", "tmat", "qpanel", "hs_fp64", "slice", "hs_split", "leg_prep", "s_legendre")}
+                    for fam in ("coeffs", "tmat", "qpanel", "hs_fp64", "slice", "hs_split", "hs_mod", "mod_crt",
+                                "leg_prep", "s_legendre")}
             fl.profile(False)
             n_l, k_ms = kern[KERNEL[prec]]
             achieved = sum(f_contract) * args.steps / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
@@ -236,6 +275,8 @@ def main():
         for p in precs:
             results[p]["rel_err"] = errs[p]
 
+    radial = radial_leg(cell, args.radial_nr, args.steps, not args.no_cpu_baseline) if args.radial_nr else None
+
     head_path = precs[0]
     head, head_method = split_path(head_path)
     r = results[head_path]
@@ -244,7 +285,7 @@ def main():
     achieved = r["contraction_tflops"]
     # the committed counters cover the default method (S with H on the matrix cores)
     traffic = read_traffic(head, cell.name) if head_method == "gemm" else None
-    slices = args.slices or (6 if head == "i8" else 5)
+    slices = args.slices or ((r["tuned"] or {}).get("slices") or DEFAULT_SLICES.get(head, 0))
     roof = {"bound": "mfma", "kernel": KERNEL[head], "achieved": achieved, "peak": PEAKS[head],
             "unit": "TFLOP/s" if head == "fp64" else "TOP/s",
             "frac": (achieved / PEAKS[head]) if achieved else None, "traffic": traffic,
@@ -254,12 +295,13 @@ def main():
                                  if head_method == "gemm" else
                                  "FP64-equivalent flops of the H upper triangle (8 K N(N+1)); S by the addition theorem")}
     if head != "fp64" and achieved:
-        ex = achieved * executed_per_flop(slices)
-        roof.update({"executed_ops_per_flop": executed_per_flop(slices), "executed_achieved": ex,
+        ex = achieved * executed_per_flop(slices, head)
+        roof.update({"executed_ops_per_flop": executed_per_flop(slices, head), "executed_achieved": ex,
                      "executed_frac": ex / PEAKS[head], "slices": slices})
     ceil = None if args.no_ceiling else mfma_ceiling()
     if ceil:
-        key = {"i8": "i8_random_TOPs", "bf16": "bf16_random_TFLOPs", "fp64": "f64_random_TFLOPs"}[head]
+        key = {"i8": "i8_random_TOPs", "i8mod": "i8_random_TOPs", "bf16": "bf16_random_TFLOPs",
+               "fp64": "f64_random_TFLOPs"}[head]
         ref = roof.get("executed_achieved", achieved)
         roof["ceiling_random_operands"] = {
             "rates": ceil, "value": ceil[key],
@@ -270,7 +312,7 @@ def main():
         "metric": "H+S gen time/k-point & TFLOP/s: split-prec vs FP64 MFMA at ≤1e-10 rel err",
         "value": r["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "bf16": "bf16", "i8": "i8"}[head], "data": "synthetic",
+        "dtype": {"fp64": "f64", "bf16": "bf16", "i8": "i8", "i8mod": "i8"}[head], "data": "synthetic",
         "speedup_vs_fp64": (results["fp64"]["ms_per_step"] / r["ms_per_step"]) if "fp64" in results and head_path != "fp64" else None,
         "config": {"workload": cell.name, "n_atoms": cell.n_atoms, "n_types": cell.n_types, "K": kr,
                    "lmax": int(cell.lmax.max()), "lpot": cell.lpot, "n_kpoints": nk,
@@ -280,6 +322,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": base,
         "paths": results,
+        "radial_setup": radial,
     }
     print(json.dumps(line), flush=True)
 

@@ -69,12 +69,23 @@ typedef enum {
  *   SPLIT_I8    the same with int8 digits (first in [-127, 127], later in [-64, 64]) and exact
  *               int32 accumulation over 4096 rows.
  * Split precisions take 3..6 digits (FLAPW_ERR_UNSUPPORTED otherwise); 0 selects the tuned or
- * default count (6, which meets a 1e-10 relative Frobenius error on the tested workloads). */
+ * default count (6, which meets a 1e-10 relative Frobenius error on the tested workloads).
+ *   SPLIT_I8_MOD  modular split: each operand column is scaled by a power of two so that its
+ *               2-norm is below 2^B and rounded to integers; the exact integer products are
+ *               computed modulo `slices` pairwise coprime odd moduli <= 255 (one int8 matrix-core
+ *               product per modulus, int32 accumulation) and rebuilt by the Chinese remainder
+ *               theorem in FP64 (B = min(50, floor((log2 M - 3)/2)), M the product of the
+ *               moduli).  Takes 8..14 moduli (FLAPW_ERR_UNSUPPORTED for 1..7); 0 selects the
+ *               tuned or default count (11).  Needs, per k-point in flight, 2 `slices` bytes per
+ *               element of each of three 2K x N operands plus 64 `slices` KiB per 128 x 128
+ *               output tile of S and of H. */
 typedef enum {
     FLAPW_PREC_FP64 = 0,
     FLAPW_PREC_SPLIT_BF16 = 1,
-    FLAPW_PREC_SPLIT_I8 = 2
+    FLAPW_PREC_SPLIT_I8 = 2,
+    FLAPW_PREC_SPLIT_I8_MOD = 3
 } flapw_prec;
+#define FLAPW_MODULI_CAP 14        /* largest number of moduli of FLAPW_PREC_SPLIT_I8_MOD */
 
 #define FLAPW_LMAX_CAP 12          /* largest supported l_max per type */
 #define FLAPW_LPOT_CAP 12          /* largest supported l'' of the non-spherical potential */
@@ -285,8 +296,8 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
  * HIP events on the launch stream around every launch of its kernels.  flapw_profile_query
  * waits for the recorded events of one kernel family and returns the number of launches and
  * their summed duration in milliseconds since the last flapw_profile_enable(h, 1).
- * Families: "coeffs", "tmat", "qpanel", "repack", "hs_fp64", "slice", "hs_split", "leg_prep",
- * "s_legendre", "graph"
+ * Families: "coeffs", "tmat", "qpanel", "repack", "hs_fp64", "slice", "hs_split", "hs_mod",
+ * "mod_crt", "leg_prep", "s_legendre", "radial", "graph"
  * (a whole flapw_plan_launch; kernels inside a graph are not timed one by one).
  * Errors: FLAPW_ERR_ARG for an unknown family or NULL output pointer. */
 flapw_status flapw_profile_enable(flapw_handle h, int on);

@@ -345,7 +345,26 @@ void build_tiles(const std::vector<int> &np_tiles, int m0, int m1, std::vector<T
     for (int b = 0; b < n; ++b) out[b] = order[start[b % 8] + b / 8];
 }
 
-int default_slices(flapw_prec) { return 6; }
+int default_slices(flapw_prec prec) { return prec == FLAPW_PREC_SPLIT_I8_MOD ? 11 : 6; }
+
+// Precision and digit (modulus) count of a call: FLAPW_ERR_ARG for an unknown precision or a count
+// outside 0..FLAPW_MODULI_CAP, FLAPW_ERR_UNSUPPORTED for a count the precision does not implement.
+flapw_status check_prec(flapw_handle h, flapw_prec prec, int slices)
+{
+    if (prec != FLAPW_PREC_FP64 && prec != FLAPW_PREC_SPLIT_BF16 && prec != FLAPW_PREC_SPLIT_I8 &&
+        prec != FLAPW_PREC_SPLIT_I8_MOD)
+        return fail(h, FLAPW_ERR_ARG, "unknown precision");
+    if (prec == FLAPW_PREC_SPLIT_I8_MOD) {
+        if (slices < 0 || slices > FLAPW_MODULI_CAP) return fail(h, FLAPW_ERR_ARG, "modulus count out of range");
+        if (slices != 0 && slices < kModMin)
+            return fail(h, FLAPW_ERR_UNSUPPORTED, "modular split precision supports 8..14 moduli");
+        return FLAPW_OK;
+    }
+    if (slices < 0 || slices > FLAPW_SLICES_CAP) return fail(h, FLAPW_ERR_ARG, "slices out of range");
+    if (prec != FLAPW_PREC_FP64 && slices != 0 && (slices < 3 || slices > 6))
+        return fail(h, FLAPW_ERR_UNSUPPORTED, "split precision supports 3..6 digits");
+    return FLAPW_OK;
+}
 
 // bytes per digit: int8 digits 1, bf16 digits 2
 int digit_bytes(flapw_prec prec) { return prec == FLAPW_PREC_SPLIT_BF16 ? 2 : 1; }
@@ -391,6 +410,68 @@ DigitArea digit_area(void *base, long long kp2, long long np, int s, int eb)
     unsigned char *b = (unsigned char *)base;
     return DigitArea{(int8_t *)b, (int8_t *)(b + one), (int8_t *)(b + 2 * one), (int *)(b + 3 * one),
                      (int *)(b + 3 * one + ex), (int *)(b + 3 * one + 2 * ex)};
+}
+
+// Residue storage of one problem of the modular path: planes of P, d.P and Q (npm columns,
+// np rounded up to the 128-column tile), their column exponents, and the residue tiles.
+struct ModArea {
+    int8_t *L, *RS, *RH;
+    int *eL, *eRS, *eRH;
+    int8_t *res;
+    long long npm;
+};
+
+long long mod_area_bytes(long long kp2, long long np, int nm)
+{
+    const long long npm = round_up(np, kModTile);
+    return 3 * round_up(mod_digit_bytes(kp2, npm, nm), 256) + 3 * round_up(npm * 4, 256) +
+           round_up(mod_scratch_bytes(npm, nm), 256);
+}
+
+ModArea mod_area(void *base, long long kp2, long long np, int nm)
+{
+    const long long npm = round_up(np, kModTile);
+    const long long one = round_up(mod_digit_bytes(kp2, npm, nm), 256), ex = round_up(npm * 4, 256);
+    unsigned char *b = (unsigned char *)base;
+    return ModArea{(int8_t *)b,
+                   (int8_t *)(b + one),
+                   (int8_t *)(b + 2 * one),
+                   (int *)(b + 3 * one),
+                   (int *)(b + 3 * one + ex),
+                   (int *)(b + 3 * one + 2 * ex),
+                   (int8_t *)(b + 3 * one + 3 * ex),
+                   npm};
+}
+
+ModProblemDev mod_problem(const ModArea &ma, double2 *H, double2 *S, long long ldh, int n, long long kp2)
+{
+    const long long t = ma.npm / kModTile;
+    return ModProblemDev{ma.L, ma.RS, ma.RH, ma.eL, ma.eRS, ma.eRH, H, S, ma.res, ldh, n, (int)kp2,
+                         (int)(ma.npm / 32), (int)(t * (t + 1) / 2)};
+}
+
+flapw_status mod_slice_problem(flapw_handle h, const ProblemDev &pb, long long np, const ModArea &ma,
+                               const ModTable &mt, hipStream_t st)
+{
+    ProfScope prof(h, "slice", st);
+    hipError_t e = launch_mod_slice(pb.P, pb.Q, pb.d, pb.ldp, pb.kp2, (int)np, (int)ma.npm, mt, ma.eL, ma.eRS, ma.eRH,
+                                    ma.L, ma.RS, ma.RH, st);
+    if (e != hipSuccess) return dev_fail(h, e, "residue slicing kernels");
+    return FLAPW_OK;
+}
+
+// Modular contraction of a batch: residues per (tile, modulus), then the CRT reconstruction.
+hipError_t launch_mod_pair(flapw_handle h, const ModProblemDev *probs, const TileDev *tiles, int n_tiles,
+                           const ModTable &mt, hipStream_t st)
+{
+    hipError_t e;
+    {
+        ProfScope prof(h, "hs_mod", st);
+        e = launch_mod_contract(probs, tiles, n_tiles, mt, st);
+    }
+    if (e != hipSuccess) return e;
+    ProfScope prof(h, "mod_crt", st);
+    return launch_mod_crt(probs, tiles, n_tiles, mt, st);
 }
 
 flapw_status slice_problem(flapw_handle h, const ProblemDev &pb, long long np, int s, const DigitArea &da, bool bf16,
@@ -487,6 +568,8 @@ struct GenPlan {
     bool split = false;
     bool leg = false;            // S through the addition theorem; the contraction computes H only
     bool bf16 = false;           // split digits in bf16 (else int8)
+    bool mod = false;            // modular split precision (residues mod p_m, CRT)
+    ModTable mt{};               // its moduli (mod only)
     int lnonsph = -1;            // structured T (-1: dense T)
     int lh0 = 1 << 20;           // the Legendre kernel adds to H the L-diagonal terms of l >= lh0
     size_t ohsph = 0;            // per type and l: {aa, ab, ba, bb} of those terms
@@ -572,7 +655,9 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     p.n_types = rad->n_types;
     p.split = prec != FLAPW_PREC_FP64;
     p.bf16 = prec == FLAPW_PREC_SPLIT_BF16;
+    p.mod = prec == FLAPW_PREC_SPLIT_I8_MOD;
     p.sl = effective_slices(h, prec, L.kp2, slices);
+    if (p.mod) p.mt = make_mod_table(p.sl);
     p.band = band ? band : effective_band(h, prec, L.kp2);
     p.ldt = 2LL * L.nlmax;
     p.pref = 4.0 * kPi / std::sqrt(at->omega);
@@ -628,8 +713,9 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     if (p.split) budget = budget > panel_one ? budget - panel_one : 0;
     std::vector<size_t> need(n_k);
     for (int i = 0; i < n_k; ++i)
-        need[i] = p.split ? (size_t)digit_area_bytes(L.kp2, p.np[i], p.sl, p.bf16 ? 2 : 1)
-                          : (size_t)2 * L.kp2 * p.np[i] * sizeof(double2);
+        need[i] = p.mod     ? (size_t)mod_area_bytes(L.kp2, p.np[i], p.sl)
+                  : p.split ? (size_t)digit_area_bytes(L.kp2, p.np[i], p.sl, p.bf16 ? 2 : 1)
+                            : (size_t)2 * L.kp2 * p.np[i] * sizeof(double2);
     p.off.assign(n_k, 0);
     size_t biggest = 0;
     for (int i0 = 0; i0 < n_k;) {
@@ -677,7 +763,14 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
         std::vector<int> npt;
         std::vector<ProblemDev> probs;
         std::vector<SplitProblemDev> sprobs;
+        std::vector<ModProblemDev> mprobs;
         for (int i = bt.i0; i < bt.i1; ++i) {
+            if (p.mod) {
+                const ModArea ma = mod_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl);
+                npt.push_back((int)(ma.npm / kModTile));
+                mprobs.push_back(mod_problem(ma, (double2 *)H[i], (double2 *)S[i], (long long)ldh[i], n_g[i], L.kp2));
+                continue;
+            }
             npt.push_back((int)(p.np[i] / kTile));
             if (p.split) {
                 const DigitArea da = digit_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl, p.bf16 ? 2 : 1);
@@ -692,7 +785,9 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
         std::vector<TileDev> tiles;
         if (p.split) build_tiles(npt, p.leg ? 1 : 0, 2, tiles, p.band);
         else build_tiles(npt, 0, 1, tiles, p.band);
-        bt.o_probs = p.split ? put(hd, sprobs.data(), sprobs.size()) : put(hd, probs.data(), probs.size());
+        bt.o_probs = p.mod     ? put(hd, mprobs.data(), mprobs.size())
+                     : p.split ? put(hd, sprobs.data(), sprobs.size())
+                               : put(hd, probs.data(), probs.size());
         bt.o_tiles = put(hd, tiles.data(), tiles.size());
         bt.n_tiles = (int)tiles.size();
     }
@@ -753,14 +848,22 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
             }
             if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
             if (p.split) {
-                const DigitArea da = digit_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl, p.bf16 ? 2 : 1);
                 const ProblemDev pd{P, Q, (const double *)(p.tables + p.od), nullptr, nullptr, L.kp2, 0, p.ng[i],
                                     (int)L.kp2};
-                if ((st = slice_problem(h, pd, p.np[i], p.sl, da, p.bf16, s)) != FLAPW_OK) return st;
+                if (p.mod) {
+                    const ModArea ma = mod_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl);
+                    if ((st = mod_slice_problem(h, pd, p.np[i], ma, p.mt, s)) != FLAPW_OK) return st;
+                } else {
+                    const DigitArea da = digit_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl, p.bf16 ? 2 : 1);
+                    if ((st = slice_problem(h, pd, p.np[i], p.sl, da, p.bf16, s)) != FLAPW_OK) return st;
+                }
             }
         }
         hipError_t e;
-        if (p.split) {
+        if (p.mod) {
+            e = launch_mod_pair(h, (const ModProblemDev *)(p.desc + bt.o_probs), (const TileDev *)(p.desc + bt.o_tiles),
+                                bt.n_tiles, p.mt, s);
+        } else if (p.split) {
             ProfScope prof(h, "hs_split", s);
             e = launch_split_any(p.bf16, (const SplitProblemDev *)(p.desc + bt.o_probs),
                                  (const TileDev *)(p.desc + bt.o_tiles), bt.n_tiles, p.sl, s);
@@ -783,11 +886,8 @@ flapw_status check_generate(flapw_handle h, int n_k, const double *k, const int 
 {
     if (n_k < 1) return fail(h, FLAPW_ERR_ARG, "n_k must be >= 1");
     if (!k || !n_g || !g || !H || !S || !ldh) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
-    if (prec != FLAPW_PREC_FP64 && prec != FLAPW_PREC_SPLIT_BF16 && prec != FLAPW_PREC_SPLIT_I8)
-        return fail(h, FLAPW_ERR_ARG, "unknown precision");
-    if (slices < 0 || slices > FLAPW_SLICES_CAP) return fail(h, FLAPW_ERR_ARG, "slices out of range");
-    if (prec != FLAPW_PREC_FP64 && slices != 0 && (slices < 3 || slices > 6))
-        return fail(h, FLAPW_ERR_UNSUPPORTED, "split precision supports 3..6 digits");
+    flapw_status pst = check_prec(h, prec, slices);
+    if (pst != FLAPW_OK) return pst;
     for (int i = 0; i < n_k; ++i) {
         if (n_g[i] < 1) return fail(h, FLAPW_ERR_ARG, "n_g must be >= 1");
         if (!g[i] || !H[i] || !S[i]) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
@@ -814,10 +914,12 @@ flapw_status time_contraction(flapw_handle h, const GenPlan &p, int cap, float *
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {     // first launch warms caches and code
         e = hipEventRecord(e0, nullptr);
         if (e == hipSuccess)
-            e = p.split ? launch_split_any(p.bf16, (const SplitProblemDev *)(p.desc + bt.o_probs),
-                                           (const TileDev *)(p.desc + bt.o_tiles), n, p.sl, nullptr)
-                        : launch_hs_fp64((const ProblemDev *)(p.desc + bt.o_probs), (const TileDev *)(p.desc + bt.o_tiles),
-                                         n, !p.leg, nullptr);
+            e = p.mod     ? launch_mod_contract((const ModProblemDev *)(p.desc + bt.o_probs),
+                                                (const TileDev *)(p.desc + bt.o_tiles), n, p.mt, nullptr)
+                : p.split ? launch_split_any(p.bf16, (const SplitProblemDev *)(p.desc + bt.o_probs),
+                                             (const TileDev *)(p.desc + bt.o_tiles), n, p.sl, nullptr)
+                          : launch_hs_fp64((const ProblemDev *)(p.desc + bt.o_probs),
+                                           (const TileDev *)(p.desc + bt.o_tiles), n, !p.leg, nullptr);
         if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
@@ -947,7 +1049,11 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
             if ((e = scratch.alloc(&buf[i], mat)) != hipSuccess) return dev_fail(h, e, "allocating tuner outputs");
         std::vector<double2> Hr((size_t)n_acc * n_acc), Sr(Hr.size()), Hc(Hr.size()), Sc(Hr.size());
         const long ldn = n_acc;
-        for (int s = 0; s <= 6; s = s ? s + 1 : 3) {          // s = 0 (FP64 reference), then 3..6 digits
+        // candidate 0: the FP64 reference; then 3..6 digits, or 10..13 moduli
+        const int c0 = prec == FLAPW_PREC_SPLIT_I8_MOD ? 10 : 3;
+        const int cand[5] = {0, c0, c0 + 1, c0 + 2, c0 + 3};
+        for (int ci = 0; ci < 5; ++ci) {
+            const int s = cand[ci];
             flapw_z *Hp = (flapw_z *)buf[s ? 2 : 0], *Sp = (flapw_z *)buf[s ? 3 : 1];
             GenPlan p;
             st = prepare_generate(h, 1, k, &n_acc, &g, at, rad, pot, &Hp, &Sp, &ldn, s ? prec : FLAPW_PREC_FP64, s, 4, false, b,
@@ -959,10 +1065,13 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
             if (e != hipSuccess) return dev_fail(h, e, "reading tuner outputs");
             if (!s) continue;
             const double err = std::max(upper_relfro(Hc, Hr, n_acc), upper_relfro(Sc, Sr, n_acc));
-            if (digit_err) digit_err[s - 3] = err;
+            if (digit_err) digit_err[ci - 1] = err;
             if (!chosen && err <= 0.25 * tol) chosen = s;
         }
-        if (!chosen) return fail(h, FLAPW_ERR_UNSUPPORTED, "no digit count in 3..6 meets the tolerance");
+        if (!chosen)
+            return fail(h, FLAPW_ERR_UNSUPPORTED, prec == FLAPW_PREC_SPLIT_I8_MOD
+                                                      ? "no modulus count in 10..13 meets the tolerance"
+                                                      : "no digit count in 3..6 meets the tolerance");
     }
     // tile band: time a prefix of the full contraction of this k-point with every candidate band
     const size_t mat = (size_t)n_g * n_g * sizeof(double2);
@@ -1015,8 +1124,8 @@ flapw_status flapw_profile_query(flapw_handle h, const char *family, int *launch
 {
     if (!h) return FLAPW_ERR_ARG;
     if (!family || !launches || !total_ms) return fail(h, FLAPW_ERR_ARG, "NULL argument");
-    static const char *known[] = {"coeffs", "tmat",  "qpanel",   "repack",     "hs_fp64",
-                                  "slice",  "hs_split", "graph", "leg_prep", "s_legendre"};
+    static const char *known[] = {"coeffs",   "tmat",  "qpanel",   "repack",     "hs_fp64", "slice",
+                                  "hs_split", "hs_mod", "mod_crt", "graph", "leg_prep", "s_legendre", "radial"};
     bool ok = false;
     for (const char *k : known) ok = ok || std::strcmp(k, family) == 0;
     if (!ok) return fail(h, FLAPW_ERR_ARG, std::string("unknown kernel family ") + family);
@@ -1094,12 +1203,9 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
     if (!h) return FLAPW_ERR_ARG;
     if (!A || !B || !T || !H || !S) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
     if (n_g < 1) return fail(h, FLAPW_ERR_ARG, "n_g must be >= 1");
-    if (prec != FLAPW_PREC_FP64 && prec != FLAPW_PREC_SPLIT_BF16 && prec != FLAPW_PREC_SPLIT_I8)
-        return fail(h, FLAPW_ERR_ARG, "unknown precision");
-    if (slices < 0 || slices > FLAPW_SLICES_CAP) return fail(h, FLAPW_ERR_ARG, "slices out of range");
-    if (prec != FLAPW_PREC_FP64 && slices != 0 && (slices < 3 || slices > 6))
-        return fail(h, FLAPW_ERR_UNSUPPORTED, "split precision supports 3..6 digits");
-    flapw_status st = check_radial(h, rad);
+    flapw_status st = check_prec(h, prec, slices);
+    if (st != FLAPW_OK) return st;
+    st = check_radial(h, rad);
     if (st != FLAPW_OK) return st;
     if ((st = check_atoms(h, at, rad, false)) != FLAPW_OK) return st;
     Layout L;
@@ -1152,6 +1258,25 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
     const int band = effective_band(h, prec, L.kp2);
     if (prec == FLAPW_PREC_FP64) return run_fp64(h, {pd}, npt, band, s);
     const int sl = effective_slices(h, prec, L.kp2, slices);
+    if (prec == FLAPW_PREC_SPLIT_I8_MOD) {
+        e = h->digits.ensure((size_t)mod_area_bytes(L.kp2, np, sl));
+        if (e != hipSuccess) return dev_fail(h, e, "allocating residue buffer");
+        const ModArea ma = mod_area(h->digits.p, L.kp2, np, sl);
+        const ModTable mt = make_mod_table(sl);
+        if ((st = mod_slice_problem(h, pd, np, ma, mt, s)) != FLAPW_OK) return st;
+        std::vector<TileDev> tiles;
+        build_tiles({(int)(ma.npm / kModTile)}, 0, 2, tiles, band);
+        const ModProblemDev mp = mod_problem(ma, (double2 *)H, (double2 *)S, ldh, n_g, L.kp2);
+        auto &hs = h->host_sdesc;
+        hs.clear();
+        const size_t op = put(hs, &mp, 1);
+        const size_t ot = put(hs, tiles.data(), tiles.size());
+        if ((st = upload(h, h->sdesc, hs, s)) != FLAPW_OK) return st;
+        unsigned char *db = (unsigned char *)h->sdesc.p;
+        e = launch_mod_pair(h, (const ModProblemDev *)(db + op), (const TileDev *)(db + ot), (int)tiles.size(), mt, s);
+        if (e != hipSuccess) return dev_fail(h, e, "S/H modular split kernels");
+        return FLAPW_OK;
+    }
     const int eb = digit_bytes(prec);
     e = h->digits.ensure((size_t)digit_area_bytes(L.kp2, np, sl, eb));
     if (e != hipSuccess) return dev_fail(h, e, "allocating digit buffer");

@@ -139,6 +139,44 @@ hipError_t launch_s_legendre(const double *khat, const double *ab, const double2
                              double scale, double2 *S, long long lds, const double *ud_norm2, const double *hsph,
                              int lh0, double2 *H, long long ldh, hipStream_t s);
 
+// Modular split precision (split_mod.hip).  Moduli p_m, 1/p_m as double-double, the CRT
+// constants w_m = (M/p_m)^-1 mod p_m, M = prod p_m as double-double, and the integer bits B.
+constexpr int kModCap = 14;
+constexpr int kModMin = 8;
+constexpr int kModTile = 128;   // output tile edge of the modular contraction
+struct ModTable {
+    int nm;
+    int bits;
+    int p[kModCap];
+    int w[kModCap];
+    double inv_p[kModCap];
+    double inv_p_lo[kModCap];
+    double M_hi, M_lo;
+};
+// One k-point of the modular contraction.  L, RS, RH: residue planes (layout in split_mod.hip),
+// ncb 32-column blocks wide; res: residue tiles, 2 ntri slots per modulus (S tiles, then H).
+struct ModProblemDev {
+    const int8_t *L, *RS, *RH;
+    const int *eL, *eRS, *eRH;
+    double2 *H, *S;
+    int8_t *res;
+    long long ldh;
+    int n;
+    int kp2;
+    int ncb;
+    int ntri;
+};
+ModTable make_mod_table(int nm);
+long long mod_digit_bytes(long long kp2, long long npm, int nm);
+long long mod_scratch_bytes(long long npm, int nm);
+hipError_t launch_mod_slice(const double2 *P, const double2 *Q, const double *d, long long ld, int kp2, int np,
+                            int npm, const ModTable &mt, int *eL, int *eRS, int *eRH, int8_t *L, int8_t *RS,
+                            int8_t *RH, hipStream_t s);
+hipError_t launch_mod_contract(const ModProblemDev *probs, const TileDev *tiles, int n_tiles, const ModTable &mt,
+                               hipStream_t s);
+hipError_t launch_mod_crt(const ModProblemDev *probs, const TileDev *tiles, int n_tiles, const ModTable &mt,
+                          hipStream_t s);
+
 // Radial functions and radial integrals (radial.hip).  fun: scratch of radial_fun_bytes();
 // bnd: n_types x kLStride x 5 (u, u', udot, udot', ||udot||^2); i_*: the four flapw_potential
 // tables, zero-filled by the caller.

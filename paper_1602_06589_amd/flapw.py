@@ -26,8 +26,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libflapw_hip.so")
 
-FP64, SPLIT_BF16, SPLIT_I8 = 0, 1, 2
-PRECISIONS = {"fp64": FP64, "bf16": SPLIT_BF16, "i8": SPLIT_I8}
+FP64, SPLIT_BF16, SPLIT_I8, SPLIT_I8_MOD = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "bf16": SPLIT_BF16, "i8": SPLIT_I8, "i8mod": SPLIT_I8_MOD}
 S_METHODS = {"gemm": 0, "legendre": 1}
 
 _STATUS = {0: "FLAPW_OK", -1: "FLAPW_ERR_ARG", -2: "FLAPW_ERR_WRONSKIAN", -3: "FLAPW_ERR_NOT_HERMITIAN",
@@ -330,7 +330,8 @@ class Flapw:
 
     def tune(self, system, k, g, prec="i8", tol: float = 1e-10):
         """Runs the autotuner on one k-point (g: device tensor (n_g, 3)); the handle keeps the choice.
-        Returns {"slices", "band", "digit_err" (3..6 digits), "band_ms" (bands 1, 2, 4, 8, 16)}."""
+        Returns {"slices", "band", "digit_err" (3..6 digits, or 10..13 moduli for "i8mod"),
+        "band_ms" (bands 1, 2, 4, 8, 16)}."""
         self._keep = []
         kk = _f64(k)
         rad, at, pot = self._radial(system), self._atoms(system), self._potential(system)

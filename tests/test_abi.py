@@ -157,7 +157,11 @@ def test_plan_validation(handle):
     assert out.value is None                                          # cleared on failure
     assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 1, 2, ctypes.byref(out)) == -6
     assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 2, 7, ctypes.byref(out)) == -6
-    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 3, 0, ctypes.byref(out)) == -1
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 4, 0, ctypes.byref(out)) == -1
+    # modular split: 8..14 moduli; 1..7 unsupported, beyond the cap an argument error
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 3, 7, ctypes.byref(out)) == -6
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 3, 15, ctypes.byref(out)) == -1
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 3, -1, ctypes.byref(out)) == -1
     assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 0, 0, None) == -1
     assert handle._lib.flapw_plan_launch(None, None) == -1
     assert handle._lib.flapw_plan_destroy(None) == -1

@@ -1,0 +1,167 @@
+"""GPU parity of the modular split precision (residues modulo pairwise coprime moduli <= 256 on
+the int8 matrix cores, rebuilt by the Chinese remainder theorem) against the FP64 oracle.
+
+Bar: relative Frobenius error <= 1e-10 per matrix (H and S separately) with the default 11
+moduli; the error falls with every extra modulus, within 2^(10-B) where B is the integer bit
+width the moduli allow."""
+import math
+
+import numpy as np
+import pytest
+
+import synthcells
+
+pytestmark = pytest.mark.gpu
+
+TOL_SPLIT = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_06589_amd import Flapw
+    f = Flapw()
+    yield f
+    f.close()
+
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+
+
+def _mixed(seed=12, n_g=517, n_k=1):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, 9.0, size=(5, 3))
+    return synthcells.custom_cell("mixed", 9.0, pos, np.array([0, 1, 0, 2, 1], np.int32), [5, 3, 8], [2.0, 1.7, 1.5],
+                                  4, [n_g + 37 * i for i in range(n_k)], [seed], rotations="random")
+
+
+def _upper(M):
+    U = np.triu(M.T)
+    return U + np.triu(U, 1).conj().T
+
+
+def _relfro(got, ref):
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def _bits(nm):
+    """Integer width B for nm moduli (pairwise coprime odd numbers, taken greedily from 255 down)."""
+    mods, c = [], 255
+    while len(mods) < nm:
+        if all(math.gcd(c, m) == 1 for m in mods):
+            mods.append(c)
+        c -= 2
+    return min(50, int(math.floor((sum(math.log2(m) for m in mods) - 3) / 2)))
+
+
+def _full_errors(ctx, oracle_lib, cell, slices=0):
+    out = ctx.hs_generate(cell, cell.kpts, [_dev(g) for g in cell.gvecs], prec="i8mod", slices=slices)
+    errs = []
+    for ik, (H, S) in enumerate(out):
+        Ho, So = oracle_lib.hs_full(cell, ik)
+        errs.append((_relfro(_upper(H.cpu().numpy()), Ho), _relfro(_upper(S.cpu().numpy()), So)))
+    return errs, out
+
+
+@pytest.mark.parametrize("which", ["c0", "mixed"])
+def test_mod_full(ctx, oracle_lib, which):
+    print(f"i8mod full {which}", flush=True)
+    cell = synthcells.config(0) if which == "c0" else _mixed()
+    errs, out = _full_errors(ctx, oracle_lib, cell)
+    for eh, es in errs:
+        assert eh < TOL_SPLIT and es < TOL_SPLIT, (eh, es)
+    H, S = out[0]
+    assert np.all(np.diag(H.cpu().numpy()).imag == 0.0)
+    assert np.all(np.diag(S.cpu().numpy()).imag == 0.0)
+
+
+def test_mod_lower_untouched(ctx):
+    import torch
+    cell = _mixed(n_g=200)
+    n = cell.n_g(0)
+    sentinel = complex(-2.0, 5.0)
+    H = torch.full((n, n + 5), sentinel, dtype=torch.complex128, device="cuda")
+    S = torch.full((n, n + 5), sentinel, dtype=torch.complex128, device="cuda")
+    ctx.hs_generate(cell, cell.kpts, [_dev(cell.gvecs[0])], prec="i8mod", out=[(H, S)])
+    for M in (H.cpu().numpy(), S.cpu().numpy()):
+        low = np.tril(np.ones((n, n), bool), -1).T
+        assert np.all(M[:, :n][low] == sentinel)
+        assert np.all(M[:, n:] == sentinel)
+
+
+def test_mod_moduli_monotone(ctx, oracle_lib):
+    """The error falls with every extra modulus down to the FP64 floor; 11 moduli meet the bar."""
+    cell = _mixed(n_g=300)
+    prev = None
+    for nm in range(8, 15):
+        (eh, es), = _full_errors(ctx, oracle_lib, cell, slices=nm)[0]
+        e = max(eh, es)
+        print(f"moduli {nm}: B {_bits(nm)} err {e:.3e}", flush=True)
+        assert e < 2.0 ** (10 - _bits(nm)) + 1e-14, (nm, e)
+        if prev is not None and prev > 1e-13:
+            assert e < prev / 4, (nm, e, prev)
+        if nm == 11:
+            assert e < TOL_SPLIT
+        prev = e
+
+
+def test_mod_batched_mixed_lmax(ctx, oracle_lib):
+    cell = _mixed(seed=21, n_g=190, n_k=3)
+    errs, _ = _full_errors(ctx, oracle_lib, cell)
+    for eh, es in errs:
+        assert eh < TOL_SPLIT and es < TOL_SPLIT
+
+
+def test_mod_contract_random_operands(ctx, oracle_lib):
+    cell = _mixed(n_g=260)
+    A, B = synthcells.random_contraction_inputs([9, 9], cell.k_rows(), 260)
+    T = ctx.build_T(cell)
+    H, S = ctx.hs_contract(cell, _dev(A.T), _dev(B.T), T, prec="i8mod")
+    Ho, So = oracle_lib.hs_block(cell, oracle_lib.tmat_all(cell), A, B, A, B)
+    assert _relfro(_upper(H.cpu().numpy()), Ho) < TOL_SPLIT
+    assert _relfro(_upper(S.cpu().numpy()), So) < TOL_SPLIT
+
+
+@pytest.mark.parametrize("lnonsph", [-1, 3])
+def test_mod_with_legendre_s(ctx, oracle_lib, lnonsph):
+    """S by the addition theorem (FP64) and H by the modular contraction, dense and structured T."""
+    from paper_1602_06589_amd import Flapw
+    cell = _mixed(seed=31, n_g=333, n_k=2)
+    with Flapw() as f:
+        f.set_s_method("legendre")
+        f.set_lnonsph(lnonsph)
+        out = f.hs_generate(cell, cell.kpts, [_dev(g) for g in cell.gvecs], prec="i8mod")
+        for ik, (H, S) in enumerate(out):
+            Ho, So = oracle_lib.hs_full(cell, ik, lnonsph=lnonsph)
+            assert _relfro(_upper(H.cpu().numpy()), Ho) < TOL_SPLIT
+            assert _relfro(_upper(S.cpu().numpy()), So) < 1e-12
+
+
+def _sampled(ctx, oracle_lib, cell, nsamp=48):
+    out = ctx.hs_generate(cell, cell.kpts, [_dev(g) for g in cell.gvecs], prec="i8mod")
+    T = oracle_lib.tmat_all(cell)
+    errs = []
+    for ik, (H, S) in enumerate(out):
+        n = cell.n_g(ik)
+        rng = np.random.default_rng(300 + ik)
+        idx = np.unique(np.concatenate([rng.choice(n, nsamp, replace=False), [0, n - 1]]))
+        Ho, So = oracle_lib.hs_sampled(cell, ik, idx, idx, T)
+        up = idx[:, None] <= idx[None, :]
+        for M, R in ((H.cpu().numpy(), Ho), (S.cpu().numpy(), So)):
+            got = M[np.ix_(idx, idx)].T
+            errs.append(float(np.linalg.norm((got - R)[up]) / np.linalg.norm(R[up])))
+    return errs
+
+
+def test_mod_c1_sampled(ctx, oracle_lib):
+    errs = _sampled(ctx, oracle_lib, synthcells.config(1))
+    assert max(errs) < TOL_SPLIT, errs
+
+
+def test_mod_c3_subset_sampled(ctx, oracle_lib):
+    errs = _sampled(ctx, oracle_lib, synthcells.config(3, n_k=3), nsamp=32)
+    assert max(errs) < TOL_SPLIT, errs
