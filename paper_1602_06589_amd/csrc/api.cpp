@@ -1501,6 +1501,7 @@ flapw_status flapw_plan_create(flapw_handle h, int n_k, const double *k, const i
     hipError_t e = init_fp64_kernels();
     if (e == hipSuccess && prec == FLAPW_PREC_SPLIT_I8) e = init_split_kernels();
     if (e == hipSuccess && prec == FLAPW_PREC_SPLIT_BF16) e = init_split_bf16_kernels();
+    if (e == hipSuccess && prec == FLAPW_PREC_SPLIT_I8_MOD) e = init_mod_kernels();
     if (e == hipSuccess && h->s_method == FLAPW_S_LEGENDRE) e = init_legendre_kernels();
     if (e != hipSuccess) return dev_fail(h, e, "kernel attributes");
     flapw_plan_s *pl = new (std::nothrow) flapw_plan_s();

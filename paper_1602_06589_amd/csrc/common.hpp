@@ -167,6 +167,7 @@ struct ModProblemDev {
     int ntri;
 };
 ModTable make_mod_table(int nm);
+hipError_t init_mod_kernels();    // dynamic-LDS attribute of the contraction (before launch or capture)
 long long mod_digit_bytes(long long kp2, long long npm, int nm);
 long long mod_scratch_bytes(long long npm, int nm);
 hipError_t launch_mod_slice(const double2 *P, const double2 *Q, const double *d, long long ld, int kp2, int np,

@@ -27,7 +27,8 @@
 //   mod_slice_kernel    residues of all moduli, stored as [modulus][32-column block][16-row chunk]
 //                       [re, im][32 columns][16 bytes] (one 1 KB MFMA fragment per chunk)
 //   hs_mod_i8_kernel    one block per (128 x 128 output tile, modulus): four waves of 64 x 64,
-//                       stages of 64 rows copied to LDS by global_load_lds; writes the tile's
+//                       stages of 64 rows copied to LDS by global_load_lds, two blocks per CU;
+//                       fragments of the next 16-row chunk read ahead of the MFMAs; writes the tile's
 //                       residues (int8, 32 KB) to the problem's scratch
 //   mod_crt_kernel      one block per tile: reads the residues of all moduli, rebuilds and
 //                       scales the FP64 values, writes the upper triangle of S or H
@@ -42,10 +43,11 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kStageRows = 64;            // complex rows per LDS stage (4 chunks of 16)
-constexpr int kRunBytes = 4 * 1024;       // one 32-column block over one stage
+constexpr int kChunks = 4;                // 16-row chunks per LDS stage
+constexpr int kStageRows = 16 * kChunks;  // complex rows per LDS stage
+constexpr int kRunBytes = kChunks * 1024; // one 32-column block over one stage
 constexpr int kStageBytes = 8 * kRunBytes;  // 4 left + 4 right column blocks
-constexpr int kFlushStages = 512;         // 512 * 64 rows * 2 * 128^2 < 2^31
+constexpr int kFlushStages = 32768 / kStageRows;  // 32768 rows * 2 * 127^2 < 2^31
 constexpr int kResTileBytes = kModTile * kModTile * 2;  // int8 residues of Re and Im
 
 // x mod p in [-(p-1)/2, (p-1)/2] for odd p and integer-valued |x| < 2^52
@@ -186,7 +188,7 @@ __device__ inline int tri_index(int ti, int tj) { return tj * (tj + 1) / 2 + ti;
 __global__ __launch_bounds__(256, 2) void hs_mod_i8_kernel(const ModProblemDev *__restrict__ probs,
                                                            const TileDev *__restrict__ tiles, ModTable mt)
 {
-    __shared__ __align__(16) unsigned char smem[2 * kStageBytes];
+    extern __shared__ __align__(16) unsigned char smem[];
     const TileDev td = tiles[blockIdx.x];
     const ModProblemDev pb = probs[td.prob];
     const int mo = blockIdx.y, mat = td.pad;
@@ -215,14 +217,17 @@ __global__ __launch_bounds__(256, 2) void hs_mod_i8_kernel(const ModProblemDev *
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][c][r] = 0;
 
-    // A stage is 8 runs of 4 KB = 32 segments of 1 KB; wave w copies chunk w of every run
-    // (segment 4 run + w), lane l's 16 bytes landing at +16 l.
+    // A stage is 8 runs of kChunks segments of 1 KB; wave w copies chunks w, w + 4, ... of every
+    // run, lane l's 16 bytes landing at +16 l.
 #define MOD_COPY(st, b)                                                                           \
     do {                                                                                          \
-        _Pragma("unroll") for (int j = 0; j < 8; ++j) {                                           \
-            const int8_t *src_ = run_base[j] + ((long long)(st) * 4 + wave) * 1024 + lane * 16;   \
+        _Pragma("unroll") for (int j = 0; j < 8; ++j)                                             \
+        _Pragma("unroll") for (int c = 0; c < kChunks / 4; ++c) {                                 \
+            const int ch_ = wave + 4 * c;                                                         \
+            const int8_t *src_ = run_base[j] + ((long long)(st) * kChunks + ch_) * 1024 + lane * 16; \
             __builtin_amdgcn_global_load_lds((const int __attribute__((address_space(1))) *)src_,   \
-                (int __attribute__((address_space(3))) *)(smem + (b) * kStageBytes + (4 * j + wave) * 1024), 16, 0, 0); \
+                (int __attribute__((address_space(3))) *)(smem + (b) * kStageBytes + j * kRunBytes + ch_ * 1024), \
+                16, 0, 0);                                                                        \
         }                                                                                         \
     } while (0)
 
@@ -237,22 +242,34 @@ __global__ __launch_bounds__(256, 2) void hs_mod_i8_kernel(const ModProblemDev *
             const int b = st & 1;
             if (st + 1 < nst) MOD_COPY(st + 1, b ^ 1);
             const unsigned char *stage = smem + b * kStageBytes;
+            const unsigned char *la = stage + (2 * wm) * kRunBytes + col * 16;
+            const unsigned char *lb = stage + (4 + 2 * wn) * kRunBytes + col * 16;
+            v4i a[2], bb[2], bs[2];
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const unsigned char *la = stage + (2 * wm) * kRunBytes + kk * 1024 + col * 16;
-                const unsigned char *lb = stage + (4 + 2 * wn) * kRunBytes + kk * 1024 + col * 16;
-                v4i a[2], an[2], bb[2], bs[2];
+            for (int i = 0; i < 2; ++i) {
+                a[i] = *reinterpret_cast<const v4i *>(la + i * kRunBytes + half * 512);
+                bb[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes + half * 512);
+                bs[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes + (1 - half) * 512);
+            }
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    a[i] = *reinterpret_cast<const v4i *>(la + i * kRunBytes + half * 512);
-                    bb[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes + half * 512);
-                    bs[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes + (1 - half) * 512);
+            for (int kk = 0; kk < kChunks; ++kk) {
+                v4i na[2], nbb[2], nbs[2];
+                if (kk + 1 < kChunks) {          // next chunk's fragments, read ahead
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        na[i] = *reinterpret_cast<const v4i *>(la + i * kRunBytes + (kk + 1) * 1024 + half * 512);
+                        nbb[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes + (kk + 1) * 1024 + half * 512);
+                        nbs[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes + (kk + 1) * 1024 + (1 - half) * 512);
+                    }
                 }
+                // keep the reads ahead of this chunk's products (the scheduler would sink them)
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
                         acc[i][j][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], bb[j], acc[i][j][0], 0, 0, 0);
+                v4i an[2];
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -262,6 +279,14 @@ __global__ __launch_bounds__(256, 2) void hs_mod_i8_kernel(const ModProblemDev *
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
                         acc[i][j][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(an[i], bs[j], acc[i][j][1], 0, 0, 0);
+                if (kk + 1 < kChunks) {
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        a[i] = na[i];
+                        bb[i] = nbb[i];
+                        bs[i] = nbs[i];
+                    }
+                }
             }
             __syncthreads();
         }
@@ -389,6 +414,15 @@ __global__ __launch_bounds__(256) void mod_crt_kernel(const ModProblemDev *__res
 
 }  // namespace
 
+hipError_t init_mod_kernels()
+{
+    static hipError_t done = hipErrorNotReady;
+    if (done == hipSuccess) return done;
+    done = hipFuncSetAttribute((const void *)hs_mod_i8_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               2 * kStageBytes);
+    return done;
+}
+
 long long mod_digit_bytes(long long kp2, long long npm, int nm) { return 2LL * nm * kp2 * npm; }
 
 long long mod_scratch_bytes(long long npm, int nm)
@@ -414,7 +448,10 @@ hipError_t launch_mod_slice(const double2 *P, const double2 *Q, const double *d,
 hipError_t launch_mod_contract(const ModProblemDev *probs, const TileDev *tiles, int n_tiles, const ModTable &mt,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL(hs_mod_i8_kernel, dim3(n_tiles, mt.nm), dim3(256), 0, s, probs, tiles, mt);
+    static_assert(2 * kStageBytes <= 163840, "LDS budget");
+    hipError_t e = init_mod_kernels();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(hs_mod_i8_kernel, dim3(n_tiles, mt.nm), dim3(256), 2 * kStageBytes, s, probs, tiles, mt);
     return hipGetLastError();
 }
 
