@@ -326,6 +326,8 @@ flapw_status build_T_impl(flapw_handle h, const flapw_radial *rad, const flapw_p
 // Tiles (prob, ti <= tj, m) for m in [m0, m1) (split precision: 0 = S, 1 = H), in bands of kBand
 // tile rows, then dealt round-robin over the 8 XCDs so that neighbours in the band order run on
 // the same XCD (and share its L2).
+void xcd_interleave(const std::vector<TileDev> &order, std::vector<TileDev> &out);
+
 void build_tiles(const std::vector<int> &np_tiles, int m0, int m1, std::vector<TileDev> &out, int kBand = 4)
 {
     std::vector<TileDev> order;
@@ -336,6 +338,29 @@ void build_tiles(const std::vector<int> &np_tiles, int m0, int m1, std::vector<T
                 for (int ti = b0; ti < std::min(b0 + kBand, tj + 1); ++ti)
                     for (int m = m0; m < m1; ++m) order.push_back(TileDev{p, ti, tj, m});
     }
+    xcd_interleave(order, out);
+}
+
+// Blocks of the modular contraction: rows 256 I .. 256 I + 255 (128-row tiles 2I, 2I + 1) by
+// columns 128 J .. 128 J + 127, for the upper triangle (2I <= J); np_tiles counts 128-column
+// tiles and is even.  Bands of kBand block rows walk the columns, as in build_tiles.
+void build_mod_tiles(const std::vector<int> &np_tiles, int m0, int m1, std::vector<TileDev> &out, int kBand)
+{
+    std::vector<TileDev> order;
+    for (int p = 0; p < (int)np_tiles.size(); ++p) {
+        const int nt = np_tiles[p], nb = nt / 2;
+        for (int b0 = 0; b0 < nb; b0 += kBand)
+            for (int tj = 2 * b0; tj < nt; ++tj)
+                for (int bi = b0; bi < std::min(b0 + kBand, tj / 2 + 1); ++bi)
+                    for (int m = m0; m < m1; ++m) order.push_back(TileDev{p, bi, tj, m});
+    }
+    xcd_interleave(order, out);
+}
+
+// Consecutive work-groups go to the 8 XCDs in turn: give XCD x the x-th contiguous eighth of the
+// ordered list, so neighbouring tiles (which share panels) meet in one L2.
+void xcd_interleave(const std::vector<TileDev> &order, std::vector<TileDev> &out)
+{
     const int n = (int)order.size();
     out.resize(n);
     const int q = n / 8, rem = n % 8;
@@ -413,7 +438,8 @@ DigitArea digit_area(void *base, long long kp2, long long np, int s, int eb)
 }
 
 // Residue storage of one problem of the modular path: planes of P, d.P and Q (npm columns,
-// np rounded up to the 128-column tile), their column exponents, and the residue tiles.
+// np rounded up to 256 = two 128-column tiles, the row extent of a contraction block), their
+// column exponents, and the residue tiles.
 struct ModArea {
     int8_t *L, *RS, *RH;
     int *eL, *eRS, *eRH;
@@ -423,14 +449,14 @@ struct ModArea {
 
 long long mod_area_bytes(long long kp2, long long np, int nm)
 {
-    const long long npm = round_up(np, kModTile);
+    const long long npm = round_up(np, 2 * kModTile);
     return 3 * round_up(mod_digit_bytes(kp2, npm, nm), 256) + 3 * round_up(npm * 4, 256) +
            round_up(mod_scratch_bytes(npm, nm), 256);
 }
 
 ModArea mod_area(void *base, long long kp2, long long np, int nm)
 {
-    const long long npm = round_up(np, kModTile);
+    const long long npm = round_up(np, 2 * kModTile);
     const long long one = round_up(mod_digit_bytes(kp2, npm, nm), 256), ex = round_up(npm * 4, 256);
     unsigned char *b = (unsigned char *)base;
     return ModArea{(int8_t *)b,
@@ -460,14 +486,15 @@ flapw_status mod_slice_problem(flapw_handle h, const ProblemDev &pb, long long n
     return FLAPW_OK;
 }
 
-// Modular contraction of a batch: residues per (tile, modulus), then the CRT reconstruction.
-hipError_t launch_mod_pair(flapw_handle h, const ModProblemDev *probs, const TileDev *tiles, int n_tiles,
-                           const ModTable &mt, hipStream_t st)
+// Modular contraction of a batch: residues per (256 x 128 block, modulus), then the CRT
+// reconstruction per 128 x 128 tile.
+hipError_t launch_mod_pair(flapw_handle h, const ModProblemDev *probs, const TileDev *blocks, int n_blocks,
+                           const TileDev *tiles, int n_tiles, const ModTable &mt, hipStream_t st)
 {
     hipError_t e;
     {
         ProfScope prof(h, "hs_mod", st);
-        e = launch_mod_contract(probs, tiles, n_tiles, mt, st);
+        e = launch_mod_contract(probs, blocks, n_blocks, mt, st);
     }
     if (e != hipSuccess) return e;
     ProfScope prof(h, "mod_crt", st);
@@ -560,6 +587,8 @@ struct GenBatch {
     int i0 = 0, i1 = 0;          // k-points [i0, i1)
     size_t o_probs = 0, o_tiles = 0;
     int n_tiles = 0;
+    size_t o_ctiles = 0;         // modular path: 128 x 128 tiles of the reconstruction
+    int n_ctiles = 0;
 };
 
 struct GenPlan {
@@ -783,8 +812,17 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
             }
         }
         std::vector<TileDev> tiles;
-        if (p.split) build_tiles(npt, p.leg ? 1 : 0, 2, tiles, p.band);
-        else build_tiles(npt, 0, 1, tiles, p.band);
+        if (p.mod) {
+            std::vector<TileDev> ctiles;
+            build_mod_tiles(npt, p.leg ? 1 : 0, 2, tiles, p.band);
+            build_tiles(npt, p.leg ? 1 : 0, 2, ctiles, p.band);
+            bt.o_ctiles = put(hd, ctiles.data(), ctiles.size());
+            bt.n_ctiles = (int)ctiles.size();
+        } else if (p.split) {
+            build_tiles(npt, p.leg ? 1 : 0, 2, tiles, p.band);
+        } else {
+            build_tiles(npt, 0, 1, tiles, p.band);
+        }
         bt.o_probs = p.mod     ? put(hd, mprobs.data(), mprobs.size())
                      : p.split ? put(hd, sprobs.data(), sprobs.size())
                                : put(hd, probs.data(), probs.size());
@@ -862,7 +900,7 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
         hipError_t e;
         if (p.mod) {
             e = launch_mod_pair(h, (const ModProblemDev *)(p.desc + bt.o_probs), (const TileDev *)(p.desc + bt.o_tiles),
-                                bt.n_tiles, p.mt, s);
+                                bt.n_tiles, (const TileDev *)(p.desc + bt.o_ctiles), bt.n_ctiles, p.mt, s);
         } else if (p.split) {
             ProfScope prof(h, "hs_split", s);
             e = launch_split_any(p.bf16, (const SplitProblemDev *)(p.desc + bt.o_probs),
@@ -1264,16 +1302,19 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
         const ModArea ma = mod_area(h->digits.p, L.kp2, np, sl);
         const ModTable mt = make_mod_table(sl);
         if ((st = mod_slice_problem(h, pd, np, ma, mt, s)) != FLAPW_OK) return st;
-        std::vector<TileDev> tiles;
+        std::vector<TileDev> blocks, tiles;
+        build_mod_tiles({(int)(ma.npm / kModTile)}, 0, 2, blocks, band);
         build_tiles({(int)(ma.npm / kModTile)}, 0, 2, tiles, band);
         const ModProblemDev mp = mod_problem(ma, (double2 *)H, (double2 *)S, ldh, n_g, L.kp2);
         auto &hs = h->host_sdesc;
         hs.clear();
         const size_t op = put(hs, &mp, 1);
+        const size_t ob = put(hs, blocks.data(), blocks.size());
         const size_t ot = put(hs, tiles.data(), tiles.size());
         if ((st = upload(h, h->sdesc, hs, s)) != FLAPW_OK) return st;
         unsigned char *db = (unsigned char *)h->sdesc.p;
-        e = launch_mod_pair(h, (const ModProblemDev *)(db + op), (const TileDev *)(db + ot), (int)tiles.size(), mt, s);
+        e = launch_mod_pair(h, (const ModProblemDev *)(db + op), (const TileDev *)(db + ob), (int)blocks.size(),
+                            (const TileDev *)(db + ot), (int)tiles.size(), mt, s);
         if (e != hipSuccess) return dev_fail(h, e, "S/H modular split kernels");
         return FLAPW_OK;
     }

@@ -26,10 +26,11 @@
 //   mod_colnorm_kernel  per column: e_c of P, of d.P (right operand of S) and of Q (right of H)
 //   mod_slice_kernel    residues of all moduli, stored as [modulus][32-column block][16-row chunk]
 //                       [re, im][32 columns][16 bytes] (one 1 KB MFMA fragment per chunk)
-//   hs_mod_i8_kernel    one block per (128 x 128 output tile, modulus): four waves of 64 x 64,
-//                       stages of 64 rows copied to LDS by global_load_lds, two blocks per CU;
-//                       fragments of the next 16-row chunk read ahead of the MFMAs; writes the tile's
-//                       residues (int8, 32 KB) to the problem's scratch
+//   hs_mod_i8_kernel    one block per (256 x 128 output block, modulus): eight waves of 64 x 64,
+//                       stages of 64 rows copied to LDS by global_load_lds into a ring of three
+//                       buffers (two stages in flight); fragments of the next 16-row chunk read
+//                       ahead of the MFMAs; writes the residues (int8, 32 KB per 128 x 128 tile)
+//                       to the problem's scratch
 //   mod_crt_kernel      one block per tile: reads the residues of all moduli, rebuilds and
 //                       scales the FP64 values, writes the upper triangle of S or H
 #include <cmath>
@@ -46,7 +47,9 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kChunks = 4;                // 16-row chunks per LDS stage
 constexpr int kStageRows = 16 * kChunks;  // complex rows per LDS stage
 constexpr int kRunBytes = kChunks * 1024; // one 32-column block over one stage
-constexpr int kStageBytes = 8 * kRunBytes;  // 4 left + 4 right column blocks
+constexpr int kStageBytes = 12 * kRunBytes;  // 8 left + 4 right column blocks
+constexpr int kRing = 3;                  // LDS stage buffers (s_waitcnt immediates use the gfx9
+                                          // encoding: vmcnt bits 3:0, expcnt 6:4, lgkmcnt 11:8)
 constexpr int kFlushStages = 32768 / kStageRows;  // 32768 rows * 2 * 127^2 < 2^31
 constexpr int kResTileBytes = kModTile * kModTile * 2;  // int8 residues of Re and Im
 
@@ -184,8 +187,25 @@ __device__ __forceinline__ int neg_bytes(int x, unsigned m7f, unsigned m01, unsi
 
 __device__ inline int tri_index(int ti, int tj) { return tj * (tj + 1) / 2 + ti; }
 
-// grid (n_tiles, nm): tile blockIdx.x of the launch's list, modulus blockIdx.y.
-__global__ __launch_bounds__(256, 2) void hs_mod_i8_kernel(const ModProblemDev *__restrict__ probs,
+// Work-group barrier of the stage ring.  Before it, the wave waits until at most `in_flight`
+// of its LDS-DMA copies are outstanding (copies complete in issue order, so the older stage has
+// landed) and until all its LDS reads have returned (so the slot about to be refilled is no
+// longer read).  Unlike __syncthreads it does not drain all copies.  The empty asm statements
+// keep the compiler from moving memory accesses across the barrier.
+template <int IN_FLIGHT>
+__device__ inline void ring_barrier()
+{
+    static_assert(IN_FLIGHT >= 0 && IN_FLIGHT < 16, "vmcnt field");
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(IN_FLIGHT | (0x7 << 4));      // vmcnt <= IN_FLIGHT, lgkmcnt 0
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// grid (n_tiles, nm): block tile blockIdx.x of the launch's list -- rows 256 I .. 256 I + 255
+// (the 128-row tiles 2I and 2I + 1), columns 128 J .. 128 J + 127 -- and modulus blockIdx.y.
+// Eight waves, wave w computing rows 64 (w >> 1) and columns 64 (w & 1) of the block tile.
+__global__ __launch_bounds__(512, 1) void hs_mod_i8_kernel(const ModProblemDev *__restrict__ probs,
                                                            const TileDev *__restrict__ tiles, ModTable mt)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -193,16 +213,12 @@ __global__ __launch_bounds__(256, 2) void hs_mod_i8_kernel(const ModProblemDev *
     const ModProblemDev pb = probs[td.prob];
     const int mo = blockIdx.y, mat = td.pad;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;     // 64 x 64 quarter of the tile
+    const int wm = wave >> 1, wn = wave & 1;
     const long long nch = pb.kp2 / 16;
     const long long mstride = (long long)pb.ncb * nch * 1024;
-    const int8_t *Lg = pb.L + mo * mstride;
-    const int8_t *Rg = (mat ? pb.RH : pb.RS) + mo * mstride;
-    // run r: left column blocks 4 ti + r (r < 4), right column blocks 4 tj + r - 4
-    const int8_t *run_base[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-        run_base[r] = r < 4 ? Lg + (4LL * td.ti + r) * nch * 1024 : Rg + (4LL * td.tj + r - 4) * nch * 1024;
+    const long long cbytes = nch * 1024;                          // one 32-column block, all rows
+    const int8_t *Lg = pb.L + mo * mstride + 8LL * td.ti * cbytes;
+    const int8_t *Rg = (mat ? pb.RH : pb.RS) + mo * mstride + 4LL * td.tj * cbytes;
     const int nst = pb.kp2 / kStageRows;
     const int pi = mt.p[mo];
     const float ipf = 1.0f / (float)pi;
@@ -217,33 +233,39 @@ __global__ __launch_bounds__(256, 2) void hs_mod_i8_kernel(const ModProblemDev *
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][c][r] = 0;
 
-    // A stage is 8 runs of kChunks segments of 1 KB; wave w copies chunks w, w + 4, ... of every
-    // run, lane l's 16 bytes landing at +16 l.
+    // A stage is 12 runs (8 left, 4 right 32-column blocks) of kChunks 1 KB segments.  Wave w
+    // copies segment (run 2q + (w >> 2), chunk w & 3) for q = 0..5, lane l's 16 bytes landing
+    // at +16 l.  Stages go round a ring of kRing buffers, kRing - 1 stages ahead.
+    const int hw = wave >> 2, cw = wave & 3;
 #define MOD_COPY(st, b)                                                                           \
     do {                                                                                          \
-        _Pragma("unroll") for (int j = 0; j < 8; ++j)                                             \
-        _Pragma("unroll") for (int c = 0; c < kChunks / 4; ++c) {                                 \
-            const int ch_ = wave + 4 * c;                                                         \
-            const int8_t *src_ = run_base[j] + ((long long)(st) * kChunks + ch_) * 1024 + lane * 16; \
+        _Pragma("unroll") for (int q = 0; q < 6; ++q) {                                           \
+            const int r_ = 2 * q + hw;                                                            \
+            const int8_t *src_ = (q < 4 ? Lg + (long long)r_ * cbytes : Rg + (long long)(r_ - 8) * cbytes) + \
+                                 ((long long)(st) * kChunks + cw) * 1024 + lane * 16;             \
             __builtin_amdgcn_global_load_lds((const int __attribute__((address_space(1))) *)src_,   \
-                (int __attribute__((address_space(3))) *)(smem + (b) * kStageBytes + j * kRunBytes + ch_ * 1024), \
+                (int __attribute__((address_space(3))) *)(smem + (b) * kStageBytes + r_ * kRunBytes + cw * 1024), \
                 16, 0, 0);                                                                        \
         }                                                                                         \
     } while (0)
 
     MOD_COPY(0, 0);
-    __syncthreads();
+    if (nst > 1) MOD_COPY(1, 1);
+    // wait for stage 0 only (vmcnt 6 = this wave's copies of stage 1 may stay in flight)
+    if (nst > 1) ring_barrier<6>();
+    else ring_barrier<0>();
 
     const int half = lane >> 5, col = lane & 31;
     const unsigned m7f = half ? 0x7f7f7f7fu : 0u, m01 = half ? 0x01010101u : 0u, m80 = half ? 0x80808080u : 0u;
+    int b = 0;                                    // ring slot of stage st
     for (int st0 = 0; st0 < nst; st0 += kFlushStages) {
         const int st1 = min(nst, st0 + kFlushStages);
         for (int st = st0; st < st1; ++st) {
-            const int b = st & 1;
-            if (st + 1 < nst) MOD_COPY(st + 1, b ^ 1);
+            const int b2 = b == 0 ? 2 : b - 1;    // slot of stage st + 2 (read last at stage st - 1)
+            if (st + 2 < nst) MOD_COPY(st + 2, b2);
             const unsigned char *stage = smem + b * kStageBytes;
             const unsigned char *la = stage + (2 * wm) * kRunBytes + col * 16;
-            const unsigned char *lb = stage + (4 + 2 * wn) * kRunBytes + col * 16;
+            const unsigned char *lb = stage + (8 + 2 * wn) * kRunBytes + col * 16;
             v4i a[2], bb[2], bs[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
@@ -288,7 +310,12 @@ __global__ __launch_bounds__(256, 2) void hs_mod_i8_kernel(const ModProblemDev *
                     }
                 }
             }
-            __syncthreads();
+            // stage st + 1 must have landed before anyone reads it; stage st + 2 may still fly
+            if (st + 1 < nst) {
+                if (st + 2 < nst) ring_barrier<6>();
+                else ring_barrier<0>();
+            }
+            b = b == 2 ? 0 : b + 1;
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -309,8 +336,12 @@ __global__ __launch_bounds__(256, 2) void hs_mod_i8_kernel(const ModProblemDev *
                 for (int r = 0; r < 16; ++r) acc[i][j][c][r] = mod_step(acc[i][j][c][r], pi, ipf);
 #undef MOD_COPY
 
-    // residues of this tile and modulus: [wave][i][j][re, im][lane][16 bytes]
-    const int slot = mat * pb.ntri + tri_index(td.ti, td.tj);
+    // residues of the wave's 64 x 64 block, stored per 128 x 128 tile (2I + (wm >> 1), J) as
+    // [wave in tile][i][j][re, im][lane][16 bytes]; tiles below the diagonal are skipped
+    const int ti = 2 * td.ti + (wm >> 1);
+    if (ti > td.tj) return;
+    const int wt = (wm & 1) * 2 + wn;
+    const int slot = mat * pb.ntri + tri_index(ti, td.tj);
     int8_t *out = pb.res + ((long long)mo * 2 * pb.ntri + slot) * kResTileBytes;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -326,7 +357,7 @@ __global__ __launch_bounds__(256, 2) void hs_mod_i8_kernel(const ModProblemDev *
                     for (int bq = 0; bq < 4; ++bq) packed |= ((unsigned)acc[i][j][c][4 * q + bq] & 0xffu) << (8 * bq);
                     w[q] = packed;
                 }
-                const int grp = ((wave * 2 + i) * 2 + j) * 2 + c;
+                const int grp = ((wt * 2 + i) * 2 + j) * 2 + c;
                 *reinterpret_cast<uint4 *>(out + ((long long)grp * 64 + lane) * 16) = make_uint4(w[0], w[1], w[2], w[3]);
             }
 }
@@ -419,7 +450,7 @@ hipError_t init_mod_kernels()
     static hipError_t done = hipErrorNotReady;
     if (done == hipSuccess) return done;
     done = hipFuncSetAttribute((const void *)hs_mod_i8_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               2 * kStageBytes);
+                               kRing * kStageBytes);
     return done;
 }
 
@@ -448,10 +479,10 @@ hipError_t launch_mod_slice(const double2 *P, const double2 *Q, const double *d,
 hipError_t launch_mod_contract(const ModProblemDev *probs, const TileDev *tiles, int n_tiles, const ModTable &mt,
                                hipStream_t s)
 {
-    static_assert(2 * kStageBytes <= 163840, "LDS budget");
+    static_assert(kRing * kStageBytes <= 163840, "LDS budget");
     hipError_t e = init_mod_kernels();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(hs_mod_i8_kernel, dim3(n_tiles, mt.nm), dim3(256), 2 * kStageBytes, s, probs, tiles, mt);
+    hipLaunchKernelGGL(hs_mod_i8_kernel, dim3(n_tiles, mt.nm), dim3(512), kRing * kStageBytes, s, probs, tiles, mt);
     return hipGetLastError();
 }
 
