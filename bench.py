@@ -2,10 +2,10 @@
 """Benchmark: H and S generation (coefficients -> T -> per-atom panels -> S/H contractions) on
 one MI355X, for the seeded synthetic workloads of synthcells.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--precs i8,fp64,i8+leg,fp64+leg]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--precs i8mod,i8,fp64,i8mod+leg,fp64+leg]
                     [--slices s]
 
-A path is a precision (i8, bf16 or fp64 for the S/H contraction) with an optional "+leg": S then
+A path is a precision (i8mod, i8, bf16 or fp64 for the S/H contraction) with an optional "+leg": S then
 comes from the addition theorem (section 3.1) and the contraction computes H alone.  The first
 path is the headline.
 A step is one flapw_hs_generate call over every k-point of the workload (the whole path).
@@ -154,7 +154,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--precs", default="i8,fp64,i8+leg,fp64+leg",
+    ap.add_argument("--precs", default="i8mod,i8,fp64,i8mod+leg,fp64+leg",
                     help="paths to measure; the first is the headline (value, roofline)")
     ap.add_argument("--slices", type=int, default=0)
     ap.add_argument("--s-method", default="gemm", choices=["gemm", "legendre"],

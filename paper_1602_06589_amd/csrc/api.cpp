@@ -477,11 +477,11 @@ ModProblemDev mod_problem(const ModArea &ma, double2 *H, double2 *S, long long l
 }
 
 flapw_status mod_slice_problem(flapw_handle h, const ProblemDev &pb, long long np, const ModArea &ma,
-                               const ModTable &mt, hipStream_t st)
+                               const ModTable &mt, bool with_s, hipStream_t st)
 {
     ProfScope prof(h, "slice", st);
     hipError_t e = launch_mod_slice(pb.P, pb.Q, pb.d, pb.ldp, pb.kp2, (int)np, (int)ma.npm, mt, ma.eL, ma.eRS, ma.eRH,
-                                    ma.L, ma.RS, ma.RH, st);
+                                    ma.L, ma.RS, ma.RH, with_s, st);
     if (e != hipSuccess) return dev_fail(h, e, "residue slicing kernels");
     return FLAPW_OK;
 }
@@ -890,7 +890,7 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
                                     (int)L.kp2};
                 if (p.mod) {
                     const ModArea ma = mod_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl);
-                    if ((st = mod_slice_problem(h, pd, p.np[i], ma, p.mt, s)) != FLAPW_OK) return st;
+                    if ((st = mod_slice_problem(h, pd, p.np[i], ma, p.mt, !p.leg, s)) != FLAPW_OK) return st;
                 } else {
                     const DigitArea da = digit_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl, p.bf16 ? 2 : 1);
                     if ((st = slice_problem(h, pd, p.np[i], p.sl, da, p.bf16, s)) != FLAPW_OK) return st;
@@ -1301,7 +1301,7 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
         if (e != hipSuccess) return dev_fail(h, e, "allocating residue buffer");
         const ModArea ma = mod_area(h->digits.p, L.kp2, np, sl);
         const ModTable mt = make_mod_table(sl);
-        if ((st = mod_slice_problem(h, pd, np, ma, mt, s)) != FLAPW_OK) return st;
+        if ((st = mod_slice_problem(h, pd, np, ma, mt, true, s)) != FLAPW_OK) return st;
         std::vector<TileDev> blocks, tiles;
         build_mod_tiles({(int)(ma.npm / kModTile)}, 0, 2, blocks, band);
         build_tiles({(int)(ma.npm / kModTile)}, 0, 2, tiles, band);

@@ -172,7 +172,7 @@ long long mod_digit_bytes(long long kp2, long long npm, int nm);
 long long mod_scratch_bytes(long long npm, int nm);
 hipError_t launch_mod_slice(const double2 *P, const double2 *Q, const double *d, long long ld, int kp2, int np,
                             int npm, const ModTable &mt, int *eL, int *eRS, int *eRH, int8_t *L, int8_t *RS,
-                            int8_t *RH, hipStream_t s);
+                            int8_t *RH, bool with_s, hipStream_t s);   // with_s = false: no S operand
 hipError_t launch_mod_contract(const ModProblemDev *probs, const TileDev *tiles, int n_tiles, const ModTable &mt,
                                hipStream_t s);
 hipError_t launch_mod_crt(const ModProblemDev *probs, const TileDev *tiles, int n_tiles, const ModTable &mt,

@@ -132,7 +132,8 @@ __device__ inline void write_residues(const double (&v)[16], const ModTable &mt,
 }
 
 // grid (npm/32, kp2/128): thread (m = tid % 32, chunk = tid / 32) handles 16 rows of column
-// 32 blockIdx.x + m.  MODE 0: residues of P (left) and d.P (right of S); MODE 1: of Q (right of H).
+// 32 blockIdx.x + m.  MODE 0: residues of P (left) and d.P (right of S); MODE 1: of Q (right of H);
+// MODE 2: of P alone (S is not contracted).
 template <int MODE>
 __global__ __launch_bounds__(256) void mod_slice_kernel(const double2 *__restrict__ P, const double2 *__restrict__ Q,
                                                         const double *__restrict__ d, long long ld, int kp2, int np,
@@ -149,7 +150,17 @@ __global__ __launch_bounds__(256) void mod_slice_kernel(const double2 *__restric
     const long long off = (cb * nch + ch) * 1024 + m * 16;
     const long long r0 = ch * 16;
     double xr[16], xi[16];
-    if (MODE == 0) {
+    if (MODE == 2) {
+        const int e1 = eL[col];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const double2 v = col < np ? P[col * ld + r0 + r] : make_double2(0.0, 0.0);
+            xr[r] = rint(ldexp(v.x, e1));
+            xi[r] = rint(ldexp(v.y, e1));
+        }
+        write_residues(xr, mt, L + off, mstride);
+        write_residues(xi, mt, L + off + 512, mstride);
+    } else if (MODE == 0) {
         double yr[16], yi[16];
         const int e1 = eL[col], e2 = eRS[col];
 #pragma unroll
@@ -464,13 +475,16 @@ long long mod_scratch_bytes(long long npm, int nm)
 
 hipError_t launch_mod_slice(const double2 *P, const double2 *Q, const double *d, long long ld, int kp2, int np,
                             int npm, const ModTable &mt, int *eL, int *eRS, int *eRH, int8_t *L, int8_t *RS,
-                            int8_t *RH, hipStream_t s)
+                            int8_t *RH, bool with_s, hipStream_t s)
 {
     hipLaunchKernelGGL(mod_colnorm_kernel, dim3(npm), dim3(256), 0, s, P, Q, d, ld, kp2, np, mt.bits, eL, eRS, eRH);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid(npm / 32, kp2 / 128);
-    hipLaunchKernelGGL(mod_slice_kernel<0>, grid, dim3(256), 0, s, P, Q, d, ld, kp2, np, mt, eL, eRS, eRH, L, RS, RH);
+    if (with_s)
+        hipLaunchKernelGGL(mod_slice_kernel<0>, grid, dim3(256), 0, s, P, Q, d, ld, kp2, np, mt, eL, eRS, eRH, L, RS, RH);
+    else
+        hipLaunchKernelGGL(mod_slice_kernel<2>, grid, dim3(256), 0, s, P, Q, d, ld, kp2, np, mt, eL, eRS, eRH, L, RS, RH);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(mod_slice_kernel<1>, grid, dim3(256), 0, s, P, Q, d, ld, kp2, np, mt, eL, eRS, eRH, L, RS, RH);
     return hipGetLastError();

@@ -89,12 +89,12 @@ def _replay_check(ctx, oracle_lib, cell, prec, tol, fraction=None):
             assert _relfro(_upper(S.cpu().numpy()), So) < tol
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("i8", 1e-10)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("i8", 1e-10), ("i8mod", 1e-10)])
 def test_plan_replays_match_eager(ctx, oracle_lib, prec, tol):
     _replay_check(ctx, oracle_lib, _mixed(), prec, tol)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("i8", 1e-10)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("i8", 1e-10), ("i8mod", 1e-10)])
 def test_plan_one_kpoint_per_batch(ctx, oracle_lib, prec, tol):
     """A tiny work budget forces one memory batch per k-point (panels and digits reused)."""
     _replay_check(ctx, oracle_lib, _mixed(seed=8, n_g=130, n_k=3), prec, tol, fraction="1e-12")
@@ -103,7 +103,7 @@ def test_plan_one_kpoint_per_batch(ctx, oracle_lib, prec, tol):
 def test_eager_one_kpoint_per_batch_equals_grouped(ctx):
     cell = _mixed(seed=9, n_g=160, n_k=3)
     g = [_dev(x) for x in cell.gvecs]
-    for prec in ("fp64", "i8"):
+    for prec in ("fp64", "i8", "i8mod"):
         grouped = [(H.cpu().numpy(), S.cpu().numpy()) for H, S in ctx.hs_generate(cell, cell.kpts, g, prec=prec)]
         os.environ["FLAPW_WORK_FRACTION"] = "1e-12"
         try:
@@ -152,3 +152,26 @@ def test_tune_fp64_and_unreachable(ctx):
         ctx.tune(cell, cell.kpts[0], g, prec="i8", tol=1e-30)
     assert ei.value.status == -6
     assert all(math.isfinite(e) for e in ei.value.result["digit_err"])
+
+
+def test_tune_moduli_and_use(ctx, oracle_lib):
+    """Modular split: the tuner picks the smallest of 10..13 moduli meeting tol / 4."""
+    from paper_1602_06589_amd import Flapw
+    cell = _mixed(seed=46, n_g=300, n_k=1)
+    g = _dev(cell.gvecs[0])
+    Ho, So = oracle_lib.hs_full(cell, 0)
+    with Flapw() as f:
+        res = f.tune(cell, cell.kpts[0], g, prec="i8mod", tol=1e-10)
+        s = res["slices"]
+        errs = res["digit_err"]
+        assert 10 <= s <= 13 and res["band"] in (1, 2, 4, 8, 16), res
+        assert all(math.isfinite(e) for e in errs)
+        assert errs[s - 10] <= 2.5e-11 and (s == 10 or errs[s - 11] > 2.5e-11), res
+        assert all(errs[i + 1] < errs[i] for i in range(2)), errs
+        (H0, S0), = f.hs_generate(cell, cell.kpts, [g], prec="i8mod")
+        (H1, S1), = f.hs_generate(cell, cell.kpts, [g], prec="i8mod", slices=s)
+        up = _upper_mask(cell.n_g(0))
+        assert np.array_equal(H0.cpu().numpy()[up], H1.cpu().numpy()[up])
+        assert np.array_equal(S0.cpu().numpy()[up], S1.cpu().numpy()[up])
+        assert _relfro(_upper(H0.cpu().numpy()), Ho) < 1e-10
+        assert _relfro(_upper(S0.cpu().numpy()), So) < 1e-10
