@@ -9,7 +9,7 @@ import synthcells
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "i8": 1e-10, "bf16": 1e-10}
+TOL = {"fp64": 1e-12, "i8": 1e-10, "bf16": 1e-10, "i8mod": 1e-10}
 
 
 @pytest.fixture(scope="module")
@@ -60,14 +60,14 @@ def _check_full(handles, oracle_lib, cell, prec, method):
 
 
 @pytest.mark.parametrize("method", ["gemm", "legendre"])
-@pytest.mark.parametrize("prec", ["fp64", "i8", "bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "i8", "bf16", "i8mod"])
 @pytest.mark.parametrize("n_g", [1, 64, 65])
 def test_tile_edges(handles, oracle_lib, n_g, prec, method):
     _check_full(handles, oracle_lib, _cell(n_g), prec, method)
 
 
 @pytest.mark.parametrize("method", ["gemm", "legendre"])
-@pytest.mark.parametrize("prec", ["fp64", "i8", "bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "i8", "bf16", "i8mod"])
 def test_caps_single_atom(handles, oracle_lib, prec, method):
     """One atom, l_max = 12 (2 NL = 338 rows) and l''_max = 12."""
     cell = _cell(230, types=(0,), lmax=(12,), lpot=12, seed=8, a=7.0)
@@ -85,7 +85,8 @@ def test_c4_kpoint0_sampled(handles, oracle_lib):
     Ho, So = oracle_lib.hs_sampled(cell, 0, idx, idx, oracle_lib.tmat_all(cell))
     up = idx[:, None] <= idx[None, :]
     for method in ("gemm", "legendre"):
-        for prec in ("i8", "fp64"):
+        for prec in ("i8mod", "i8", "fp64"):
+            print(f"c4 k-point 0 sampled: {method} {prec}", flush=True)
             (H, S), = handles[method].hs_generate(cell, cell.kpts, g, prec=prec)
             sub_idx = _dev(idx)
             Hs = H[sub_idx][:, sub_idx].cpu().numpy().T      # entry (r, t) of the sample block

@@ -23,7 +23,7 @@ def test_stale_memory_does_not_leak():
     assert (2 * cell.k_rows()) % 256 != 0                       # there are padding rows
     g = [torch.as_tensor(np.ascontiguousarray(cell.gvecs[0]), device="cuda")]
     Ho, So = oracle.hs_full(cell, 0)
-    for prec, tol in (("fp64", 1e-12), ("i8", 1e-10), ("bf16", 1e-10)):
+    for prec, tol in (("fp64", 1e-12), ("i8", 1e-10), ("bf16", 1e-10), ("i8mod", 1e-10)):
         junk = torch.full((1 << 27,), float("nan"), dtype=torch.float64, device="cuda")   # 1 GiB of NaN
         del junk
         torch.cuda.empty_cache()

@@ -10,7 +10,7 @@ import synthcells
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "i8": 1e-10, "bf16": 1e-10}
+TOL = {"fp64": 1e-12, "i8": 1e-10, "bf16": 1e-10, "i8mod": 1e-10}
 
 
 @pytest.fixture(scope="module")
@@ -72,7 +72,7 @@ def test_build_T_structured(ctx, oracle_lib, lns):
 
 
 @pytest.mark.parametrize("method", ["gemm", "legendre"])
-@pytest.mark.parametrize("prec", ["fp64", "i8", "bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "i8", "bf16", "i8mod"])
 @pytest.mark.parametrize("lns", [0, 2, 4, 8])
 def test_generate_structured(ctx, oracle_lib, lns, prec, method):
     from paper_1602_06589_amd import Flapw
@@ -122,7 +122,7 @@ def test_structured_c2_sampled(ctx, oracle_lib):
     with Flapw() as f:
         f.set_s_method("legendre")
         f.set_lnonsph(6)
-        for prec in ("fp64", "i8"):
+        for prec in ("fp64", "i8", "i8mod"):
             (H, S), = f.hs_generate(cell, cell.kpts, [_dev(cell.gvecs[0])], prec=prec)
             for name, M, R in (("H", H.cpu().numpy(), Ho), ("S", S.cpu().numpy(), So)):
                 got = M[np.ix_(idx, idx)].T
