@@ -874,7 +874,7 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
             {
                 ProfScope prof(h, "coeffs", s);
                 e = launch_coeffs(p.kv.data() + 3 * i, p.ng[i], (int)p.np[i], p.g[i], (const AtomDev *)(p.tables + p.oa),
-                                  p.n_atoms, (const TypeDev *)(p.tables + p.ot), p.n_types, p.pref, P, P, L.kp2,
+                                  p.n_atoms, (const TypeDev *)(p.tables + p.ot), p.n_types, L.nlmax, p.pref, P, P, L.kp2,
                                   2 * L.k, L.kp2, s);
             }
             if (e != hipSuccess) return dev_fail(h, e, "coefficient kernel");
@@ -1214,7 +1214,7 @@ flapw_status flapw_coeffs(flapw_handle h, const double *k, int n_g, const double
     const double pref = 4.0 * kPi / std::sqrt(at->omega);
     ProfScope prof(h, "coeffs", s);
     hipError_t e = launch_coeffs(k, n_g, n_g, g, (const AtomDev *)(base + oa), at->n_atoms, (const TypeDev *)(base + ot),
-                                 rad->n_types, pref, (double2 *)A, (double2 *)B, ld, 0, 0, s);
+                                 rad->n_types, L.nlmax, pref, (double2 *)A, (double2 *)B, ld, 0, 0, s);
     if (e != hipSuccess) return dev_fail(h, e, "coefficient kernel");
     return FLAPW_OK;
 }

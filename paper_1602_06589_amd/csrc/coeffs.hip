@@ -75,51 +75,81 @@ __device__ void sph_bessel(int n, double x, double *j)
     for (int l = 0; l <= n; ++l) j[l] *= sc;
 }
 
-// Y_{l,m} and Y_{l,-m} for one m >= 0 and l = m..lmax at the unit vector (x, y, z), as
-// Ybar_l^m(z) (x + i y)^m with the orthonormal polynomial part from the recurrence
+// Recurrence tables for Ybar_l^m (built per work-group in LDS, indexed l^2 + l + m, m >= 0):
 //   Ybar_m^m = (-1)^m sqrt((2m+1)/(4 pi) prod_{k<=m} (2k-1)/(2k)),  Ybar_{m+1}^m = sqrt(2m+3) z Ybar_m^m,
-//   Ybar_l^m = a (z Ybar_{l-1}^m - b Ybar_{l-2}^m),  a = sqrt((4l^2-1)/(l^2-m^2)),
-//   b = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1));   Y_{l,-m} = (-1)^m conj(Y_{l,m}).
-__device__ void ylm_m(int lmax, int m, double x, double y, double z, double2 *Y)
+//   Ybar_l^m = a_lm (z Ybar_{l-1}^m - b_lm Ybar_{l-2}^m),  a_lm = sqrt((4l^2-1)/(l^2-m^2)),
+//   b_lm = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)).
+// Y_lm = Ybar_l^m (x + i y)^m and Y_{l,-m} = (-1)^m conj(Y_lm).
+struct YTables {
+    double a[kNLCap];
+    double b[kNLCap];
+    double mm[kLStride];            // Ybar_m^m
+    unsigned char lof[kNLCap];      // l of L = l^2 + l + m
+};
+
+__device__ void build_ytables(YTables &yt, int tid)
+{
+    for (int L = tid; L < kNLCap; L += kThreads) {
+        int l = 0;
+        while ((l + 1) * (l + 1) <= L) ++l;
+        yt.lof[L] = (unsigned char)l;
+        const int m = L - l * l - l;
+        double av = 0.0, bv = 0.0;
+        if (m >= 0 && l >= m + 2) {
+            av = sqrt((4.0 * l * l - 1.0) / (double)(l * l - m * m));
+            bv = sqrt(((l - 1.0) * (l - 1.0) - (double)m * m) / (4.0 * (l - 1.0) * (l - 1.0) - 1.0));
+        }
+        yt.a[L] = av;
+        yt.b[L] = bv;
+    }
+    if (tid < kLStride) {
+        const int m = tid;
+        double q = 1.0;
+        for (int k = 1; k <= m; ++k) q *= (2.0 * k - 1.0) / (2.0 * k);
+        const double v = sqrt((2.0 * m + 1.0) / (4.0 * kPi) * q);
+        yt.mm[m] = (m & 1) ? -v : v;
+    }
+}
+
+// Y_{l,m} and Y_{l,-m} for one m >= 0 and l = m..lmax at the unit vector (x, y, z).
+__device__ void ylm_m(const YTables &yt, int lmax, int m, double x, double y, double z, double2 *Y)
 {
     double pr = 1.0, pi = 0.0;
     for (int k = 0; k < m; ++k) {
-        double t = pr * x - pi * y;
+        const double t = pr * x - pi * y;
         pi = pr * y + pi * x;
         pr = t;
     }
-    double q = 1.0;
-    for (int k = 1; k <= m; ++k) q *= (2.0 * k - 1.0) / (2.0 * k);
-    double qmm = sqrt((2.0 * m + 1.0) / (4.0 * kPi) * q);
-    if (m & 1) qmm = -qmm;
-    double qm2 = 0.0, qm1 = qmm;
     const double sg = (m & 1) ? -1.0 : 1.0;
+    double qm2 = 0.0, qm1 = 0.0;
     for (int l = m; l <= lmax; ++l) {
+        const int L = l * l + l + m;
         double ql;
-        if (l == m) ql = qmm;
-        else if (l == m + 1) ql = sqrt(2.0 * m + 3.0) * z * qmm;
-        else {
-            double a = sqrt((4.0 * l * l - 1.0) / (double)(l * l - m * m));
-            double b = sqrt(((l - 1.0) * (l - 1.0) - (double)m * m) / (4.0 * (l - 1.0) * (l - 1.0) - 1.0));
-            ql = a * (z * qm1 - b * qm2);
-        }
-        if (l > m) { qm2 = qm1; qm1 = ql; }
-        double2 v = make_double2(ql * pr, ql * pi);
-        Y[l * l + l + m] = v;
+        if (l == m) ql = yt.mm[m];
+        else if (l == m + 1) ql = sqrt(2.0 * m + 3.0) * z * qm1;
+        else ql = yt.a[L] * (z * qm1 - yt.b[L] * qm2);
+        qm2 = qm1;
+        qm1 = ql;
+        const double2 v = make_double2(ql * pr, ql * pi);
+        Y[L] = v;
         if (m > 0) Y[l * l + l - m] = make_double2(sg * v.x, -sg * v.y);
     }
 }
 
+// Dynamic LDS: radial factors of A and B, [n_types][kLStride] each, then Y of the chunk's atoms,
+// [kChunk][nlmax] (nlmax = largest (lmax+1)^2 of the atom set), so the footprint follows the
+// problem's l_max rather than the library cap.
 __global__ __launch_bounds__(kThreads) void coeffs_kernel(double kx, double ky, double kz, int n_g, const double *g,
                                                           const AtomDev *atoms, int n_atoms, const TypeDev *types,
-                                                          int n_types, double pref, double2 *A, double2 *B,
+                                                          int n_types, int nlmax, double pref, double2 *A, double2 *B,
                                                           long long ld, long long zr0, long long zr1)
 {
-    __shared__ double2 radA[kTypeCap][kLStride];
-    __shared__ double2 radB[kTypeCap][kLStride];
-    __shared__ double2 Ybuf[kChunk][kNLCap];
+    extern __shared__ double2 dyn[];
+    double2 *radA = dyn, *radB = dyn + n_types * kLStride, *Ybuf = dyn + 2 * n_types * kLStride;
     __shared__ double2 phase[kChunk];
-    __shared__ int cnl[kChunk + 1];
+    __shared__ long long rowA[kChunk], rowB[kChunk];
+    __shared__ int atype[kChunk], anl[kChunk];
+    __shared__ YTables yt;
     __shared__ double kvec[4];                 // K_t (x, y, z) and |K_t|
 
     const int t = blockIdx.x;
@@ -138,6 +168,7 @@ __global__ __launch_bounds__(kThreads) void coeffs_kernel(double kx, double ky, 
         kvec[0] = x; kvec[1] = y; kvec[2] = z;
         kvec[3] = sqrt(x * x + y * y + z * z);
     }
+    build_ytables(yt, tid);
     __syncthreads();
     const double kn = kvec[3];
 
@@ -159,57 +190,56 @@ __global__ __launch_bounds__(kThreads) void coeffs_kernel(double kx, double ky, 
                 case 2: ca = make_double2(-fa, 0.0); cb = make_double2(-fb, 0.0); break;
                 default: ca = make_double2(0.0, -fa); cb = make_double2(0.0, -fb); break;
             }
-            radA[tid][l] = ca;
-            radB[tid][l] = cb;
+            radA[tid * kLStride + l] = ca;
+            radB[tid * kLStride + l] = cb;
         }
     }
 
     double khat[3] = {0.0, 0.0, 1.0};
     if (kn > 0.0) { khat[0] = kvec[0] / kn; khat[1] = kvec[1] / kn; khat[2] = kvec[2] / kn; }
 
+    // Per chunk of 16 atoms: thread (al = tid / 16, m = tid % 16) forms Y_{l,+-m} of atom al into
+    // LDS; then thread (al, j) stores rows L = j, j + 16, ... of atom al (16 consecutive rows =
+    // 256 contiguous bytes per atom and store instruction).
+    const int al = tid / 16, lane16 = tid % 16;
     for (int a0 = 0; a0 < n_atoms; a0 += kChunk) {
         const int na = min(kChunk, n_atoms - a0);
         __syncthreads();                       // previous chunk's stores are done with Ybuf
-        {
-            const int al = tid / 16, m = tid % 16;
-            if (al < na) {
-                const AtomDev &at = atoms[a0 + al];
-                const int lmax = types[at.type].lmax;
-                if (m <= lmax) {
-                    const double *R = at.rot;
-                    double x = R[0] * khat[0] + R[1] * khat[1] + R[2] * khat[2];
-                    double y = R[3] * khat[0] + R[4] * khat[1] + R[5] * khat[2];
-                    double z = R[6] * khat[0] + R[7] * khat[1] + R[8] * khat[2];
-                    ylm_m(lmax, m, x, y, z, Ybuf[al]);
-                }
-                if (m == 0) {
-                    double s, c;
-                    sincos(kvec[0] * at.pos[0] + kvec[1] * at.pos[1] + kvec[2] * at.pos[2], &s, &c);
-                    phase[al] = make_double2(c, s);
-                }
+        if (al < na) {
+            const AtomDev &at = atoms[a0 + al];
+            const int lmax = yt.lof[at.nl - 1];          // l of the atom's last row (its type's l_max,
+            const int m = lane16;                        // or less when the rows are cut)
+            if (m <= lmax) {
+                const double *R = at.rot;
+                const double x = R[0] * khat[0] + R[1] * khat[1] + R[2] * khat[2];
+                const double y = R[3] * khat[0] + R[4] * khat[1] + R[5] * khat[2];
+                const double z = R[6] * khat[0] + R[7] * khat[1] + R[8] * khat[2];
+                ylm_m(yt, lmax, m, x, y, z, Ybuf + al * nlmax);
             }
-            if (tid == 0) {
-                cnl[0] = 0;
-                for (int q = 0; q < na; ++q) cnl[q + 1] = cnl[q] + atoms[a0 + q].nl;
+            if (m == 0) {
+                double s, c;
+                sincos(kvec[0] * at.pos[0] + kvec[1] * at.pos[1] + kvec[2] * at.pos[2], &s, &c);
+                phase[al] = make_double2(c, s);
+                rowA[al] = at.rowA;
+                rowB[al] = at.rowB;
+                atype[al] = at.type;
+                anl[al] = at.nl;
             }
         }
         __syncthreads();
-        const int rows = cnl[na];
-        for (int r = tid; r < rows; r += kThreads) {
-            int al = 0;
-            while (cnl[al + 1] <= r) ++al;
-            const int L = r - cnl[al];
-            int l = (int)sqrt((double)L);
-            while (l * l > L) --l;
-            while ((l + 1) * (l + 1) <= L) ++l;
-            const AtomDev &at = atoms[a0 + al];
-            const double2 y = Ybuf[al][L];
+        if (al < na) {
             const double2 ph = phase[al];
-            // phase * conj(Y)
-            const double2 pc = make_double2(ph.x * y.x + ph.y * y.y, ph.y * y.x - ph.x * y.y);
-            const double2 ra = radA[at.type][l], rb = radB[at.type][l];
-            colA[at.rowA + L] = make_double2(ra.x * pc.x - ra.y * pc.y, ra.x * pc.y + ra.y * pc.x);
-            colB[at.rowB + L] = make_double2(rb.x * pc.x - rb.y * pc.y, rb.x * pc.y + rb.y * pc.x);
+            const int ty = atype[al], nl = anl[al];
+            double2 *dA = colA + rowA[al], *dB = colB + rowB[al];
+            for (int L = lane16; L < nl; L += 16) {
+                const int l = yt.lof[L];
+                const double2 y = Ybuf[al * nlmax + L];
+                // phase * conj(Y)
+                const double2 pc = make_double2(ph.x * y.x + ph.y * y.y, ph.y * y.x - ph.x * y.y);
+                const double2 ra = radA[ty * kLStride + l], rb = radB[ty * kLStride + l];
+                dA[L] = make_double2(ra.x * pc.x - ra.y * pc.y, ra.x * pc.y + ra.y * pc.x);
+                dB[L] = make_double2(rb.x * pc.x - rb.y * pc.y, rb.x * pc.y + rb.y * pc.x);
+            }
         }
     }
 }
@@ -217,12 +247,13 @@ __global__ __launch_bounds__(kThreads) void coeffs_kernel(double kx, double ky, 
 }  // namespace
 
 hipError_t launch_coeffs(const double kvec[3], int n_g, int n_cols, const double *g, const AtomDev *atoms, int n_atoms,
-                         const TypeDev *types, int n_types, double pref, double2 *A, double2 *B, long long ld,
-                         long long zero_rows_from, long long zero_rows_to, hipStream_t s)
+                         const TypeDev *types, int n_types, int nlmax, double pref, double2 *A, double2 *B,
+                         long long ld, long long zero_rows_from, long long zero_rows_to, hipStream_t s)
 {
-    if (n_types > kTypeCap) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(coeffs_kernel, dim3(n_cols), dim3(kThreads), 0, s, kvec[0], kvec[1], kvec[2], n_g, g, atoms,
-                       n_atoms, types, n_types, pref, A, B, ld, zero_rows_from, zero_rows_to);
+    if (n_types > kTypeCap || nlmax < 1 || nlmax > kNLCap) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double2) * (2 * (size_t)n_types * kLStride + (size_t)kChunk * nlmax);
+    hipLaunchKernelGGL(coeffs_kernel, dim3(n_cols), dim3(kThreads), lds, s, kvec[0], kvec[1], kvec[2], n_g, g, atoms,
+                       n_atoms, types, n_types, nlmax, pref, A, B, ld, zero_rows_from, zero_rows_to);
     return hipGetLastError();
 }
 

@@ -76,9 +76,10 @@ struct TileDev {
 };
 
 // kernel launchers (return hipError_t of the launch)
+// nlmax: the largest (lmax+1)^2 over the atom types (sizes the kernel's LDS)
 hipError_t launch_coeffs(const double kvec[3], int n_g, int n_cols, const double *g, const AtomDev *atoms, int n_atoms,
-                         const TypeDev *types, int n_types, double pref, double2 *A, double2 *B, long long ld,
-                         long long zero_rows_from, long long zero_rows_to, hipStream_t s);
+                         const TypeDev *types, int n_types, int nlmax, double pref, double2 *A, double2 *B,
+                         long long ld, long long zero_rows_from, long long zero_rows_to, hipStream_t s);
 
 hipError_t launch_legendre_table(int lt, int nq, const double *z, double *theta, hipStream_t s);
 // lmax_dev: l_max of each type's row blocks; lnonsph >= 0: structured T (non-spherical terms only
