@@ -77,6 +77,8 @@ def load_library(path: str = LIB_PATH):
     if _lib is None:
         if not os.path.exists(path):
             raise FileNotFoundError(f"{path} is missing: build it with paper_1602_06589_amd/build.py")
+        # torch first: its HIP runtime must be the one the library binds to (one runtime per process)
+        import torch  # noqa: F401
         lib = ctypes.CDLL(path)
         P, I, L = ctypes.c_void_p, ctypes.c_int, ctypes.c_long
         lib.flapw_create.argtypes = [ctypes.POINTER(P)]
