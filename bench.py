@@ -295,6 +295,8 @@ def main():
                                  if head_method == "gemm" else
                                  "FP64-equivalent flops of the H upper triangle (8 K N(N+1)); S by the addition theorem")}
     if head != "fp64" and achieved:
+        # the split path's FP64-equivalent rate against the FP64 matrix-core roofline it replaces
+        roof["fp64_roofline_frac"] = achieved / PEAKS["fp64"]
         ex = achieved * executed_per_flop(slices, head)
         roof.update({"executed_ops_per_flop": executed_per_flop(slices, head), "executed_achieved": ex,
                      "executed_frac": ex / PEAKS[head], "slices": slices})

@@ -238,15 +238,24 @@ __global__ __launch_bounds__(kThreads, 1) void qpanel_kernel(const double2 *__re
                                                              const int *__restrict__ atom_nl2,
                                                              const long long *__restrict__ atom_row,
                                                              const double2 *__restrict__ P, double2 *__restrict__ Q,
-                                                             long long ldp, int n_atoms, long long kp2)
+                                                             long long ldp, int n_atoms, long long kp2, int n_ct,
+                                                             int row_tiles)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     QSmem &sm = *reinterpret_cast<QSmem *>(smem_raw);
 
-    const int a = blockIdx.y;
+    // Block order: the row tiles of one (atom, column tile) unit are dispatched back to back on
+    // one XCD (work-group b runs on XCD b mod 8), so the unit's panel of P is read from HBM once
+    // and then found in that XCD's L2.  Unit u = atom * n_ct + column tile goes to XCD u mod 8.
+    const int xcd = blockIdx.x & 7, rest = blockIdx.x >> 3;
+    const int rt = rest % row_tiles;
+    const long long u = (long long)(rest / row_tiles) * 8 + xcd;
+    if (u >= (long long)(n_atoms + 1) * n_ct) return;
+    const int a = (int)(u / n_ct);
+    const int ctile = (int)(u % n_ct);
     if (a == n_atoms) {                                 // the padding rows of Q are zero, like P's
-        if (blockIdx.z != 0) return;
-        const long long c0 = (long long)blockIdx.x * kTile;
+        if (rt != 0) return;
+        const long long c0 = (long long)ctile * kTile;
         const long long pad0 = atom_row[n_atoms - 1] + atom_nl2[n_atoms - 1];
         const long long nr = kp2 - pad0;
         for (long long i = threadIdx.x; i < nr * kTile; i += blockDim.x)
@@ -254,10 +263,10 @@ __global__ __launch_bounds__(kThreads, 1) void qpanel_kernel(const double2 *__re
         return;
     }
     const int m2 = atom_nl2[a];                         // 2 NL of this atom
-    const int r0 = blockIdx.z * kTile;
+    const int r0 = rt * kTile;
     if (r0 >= m2) return;
     const long long prow = atom_row[a];
-    const long long c0 = (long long)blockIdx.x * kTile;
+    const long long c0 = (long long)ctile * kTile;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -374,13 +383,18 @@ hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, con
     if (e != hipSuccess) return e;
     // row tiles: enough for the largest atom block (2 NL <= ldt)
     const int row_tiles = (int)((ldt + kTile - 1) / kTile);
-    const dim3 grid(np / kTile, n_atoms + 1, row_tiles);       // y = n_atoms: zero the padding rows
+    const int n_ct = np / kTile;
+    // units (atom, column tile), atom n_atoms zeroing the padding rows; 8 units per group of
+    // 8 * row_tiles work-groups
+    const long long units = (long long)(n_atoms + 1) * n_ct;
+    const long long blocks = (units + 7) / 8 * 8 * row_tiles;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (real_t)
-        hipLaunchKernelGGL(qpanel_kernel<true>, grid, dim3(kThreads), sizeof(QSmem), s, T, ldt, tstride, atom_type,
-                           atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2);
+        hipLaunchKernelGGL(qpanel_kernel<true>, dim3((unsigned)blocks), dim3(kThreads), sizeof(QSmem), s, T, ldt,
+                           tstride, atom_type, atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2, n_ct, row_tiles);
     else
-        hipLaunchKernelGGL(qpanel_kernel<false>, grid, dim3(kThreads), sizeof(QSmem), s, T, ldt, tstride, atom_type,
-                           atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2);
+        hipLaunchKernelGGL(qpanel_kernel<false>, dim3((unsigned)blocks), dim3(kThreads), sizeof(QSmem), s, T, ldt,
+                           tstride, atom_type, atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2, n_ct, row_tiles);
     return hipGetLastError();
 }
 
