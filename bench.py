@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--mfma-ceiling", action="store_true",
                     help="only run the matrix-core rate microbenchmark (constant and random operands) and exit")
     ap.add_argument("--no-ceiling", action="store_true", help="skip the matrix-core rate microbenchmark")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time replays of the generation captured in a HIP graph (flapw_plan_*)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (digit count at 1e-10, tile band) on k-point 0 before timing")
     ap.add_argument("--cpu-sample", type=int, default=384)
@@ -266,6 +268,18 @@ def main():
             }
             print(f"# {path}: {ms:.2f} ms/step, {results[path]['tflops']:.2f} TFLOP/s, kernels "
                   f"{json.dumps(results[path]['kernels_ms_per_step'])}", flush=True)
+            if args.graph:
+                with fl.plan(cell, cell.kpts, gdev, prec=prec, slices=args.slices, out=out) as plan:
+                    plan.launch()
+                    torch.cuda.synchronize()
+                    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    g0.record(stream)
+                    for _ in range(args.steps):
+                        plan.launch(stream)
+                    g1.record(stream)
+                    torch.cuda.synchronize()
+                    results[path]["graph_ms_per_step"] = g0.elapsed_time(g1) / args.steps
+                print(f"# {path}: graph replay {results[path]['graph_ms_per_step']:.2f} ms/step", flush=True)
             outs[path] = (out[0][0], out[0][1])       # k-point 0 is what the CPU baseline samples
             del out
 
