@@ -50,6 +50,8 @@ constexpr int kRunBytes = kChunks * 1024; // one 32-column block over one stage
 constexpr int kStageBytes = 12 * kRunBytes;  // 8 left + 4 right column blocks
 constexpr int kRing = 3;                  // LDS stage buffers (s_waitcnt immediates use the gfx9
                                           // encoding: vmcnt bits 3:0, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kCopies = 12 * kChunks / 8; // 1 KB copies per wave per stage
+static_assert(kChunks % 2 == 0 && kRing >= 2 && kRing <= 4 && (kRing - 2) * kCopies < 16, "stage ring");
 constexpr int kFlushStages = 32768 / kStageRows;  // 32768 rows * 2 * 127^2 < 2^31
 constexpr int kResTileBytes = kModTile * kModTile * 2;  // int8 residues of Re and Im
 
@@ -213,6 +215,14 @@ __device__ inline void ring_barrier()
     asm volatile("" ::: "memory");
 }
 
+// ring_barrier with `later` younger stages allowed in flight (kCopies copies each per wave)
+__device__ inline void ring_wait(int later)
+{
+    if (later <= 0) ring_barrier<0>();
+    else if (later == 1) ring_barrier<kCopies>();
+    else ring_barrier<2 * kCopies>();
+}
+
 // grid (n_tiles, nm): block tile blockIdx.x of the launch's list -- rows 256 I .. 256 I + 255
 // (the 128-row tiles 2I and 2I + 1), columns 128 J .. 128 J + 127 -- and modulus blockIdx.y.
 // Eight waves, wave w computing rows 64 (w >> 1) and columns 64 (w & 1) of the block tile.
@@ -244,27 +254,27 @@ __global__ __launch_bounds__(512, 1) void hs_mod_i8_kernel(const ModProblemDev *
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][c][r] = 0;
 
-    // A stage is 12 runs (8 left, 4 right 32-column blocks) of kChunks 1 KB segments.  Wave w
-    // copies segment (run 2q + (w >> 2), chunk w & 3) for q = 0..5, lane l's 16 bytes landing
-    // at +16 l.  Stages go round a ring of kRing buffers, kRing - 1 stages ahead.
-    const int hw = wave >> 2, cw = wave & 3;
+    // A stage is 12 runs (8 left, 4 right 32-column blocks) of kChunks 1 KB segments, 12 kChunks
+    // segments in all.  Wave w copies segments g = w + 8q (run g / kChunks, chunk g % kChunks),
+    // q = 0..kCopies-1, lane l's 16 bytes landing at +16 l; runs 0-7 come from the left operand
+    // exactly for q < kChunks.  Stages go round a ring of kRing buffers, kRing - 1 stages ahead.
 #define MOD_COPY(st, b)                                                                           \
     do {                                                                                          \
-        _Pragma("unroll") for (int q = 0; q < 6; ++q) {                                           \
-            const int r_ = 2 * q + hw;                                                            \
-            const int8_t *src_ = (q < 4 ? Lg + (long long)r_ * cbytes : Rg + (long long)(r_ - 8) * cbytes) + \
-                                 ((long long)(st) * kChunks + cw) * 1024 + lane * 16;             \
+        _Pragma("unroll") for (int q = 0; q < kCopies; ++q) {                                     \
+            const int g_ = wave + 8 * q, r_ = g_ / kChunks, c_ = g_ % kChunks;                    \
+            const int8_t *src_ = (q < kChunks ? Lg + (long long)r_ * cbytes : Rg + (long long)(r_ - 8) * cbytes) + \
+                                 ((long long)(st) * kChunks + c_) * 1024 + lane * 16;             \
             __builtin_amdgcn_global_load_lds((const int __attribute__((address_space(1))) *)src_,   \
-                (int __attribute__((address_space(3))) *)(smem + (b) * kStageBytes + r_ * kRunBytes + cw * 1024), \
+                (int __attribute__((address_space(3))) *)(smem + (b) * kStageBytes + r_ * kRunBytes + c_ * 1024), \
                 16, 0, 0);                                                                        \
         }                                                                                         \
     } while (0)
 
-    MOD_COPY(0, 0);
-    if (nst > 1) MOD_COPY(1, 1);
-    // wait for stage 0 only (vmcnt 6 = this wave's copies of stage 1 may stay in flight)
-    if (nst > 1) ring_barrier<6>();
-    else ring_barrier<0>();
+    // stages 0 .. kRing - 2 in flight; wait for stage 0 (later stages may stay in flight)
+#pragma unroll
+    for (int q = 0; q + 1 < kRing; ++q)
+        if (q < nst) MOD_COPY(q, q);
+    ring_wait(min(kRing - 2, nst - 1));
 
     const int half = lane >> 5, col = lane & 31;
     const unsigned m7f = half ? 0x7f7f7f7fu : 0u, m01 = half ? 0x01010101u : 0u, m80 = half ? 0x80808080u : 0u;
@@ -272,8 +282,9 @@ __global__ __launch_bounds__(512, 1) void hs_mod_i8_kernel(const ModProblemDev *
     for (int st0 = 0; st0 < nst; st0 += kFlushStages) {
         const int st1 = min(nst, st0 + kFlushStages);
         for (int st = st0; st < st1; ++st) {
-            const int b2 = b == 0 ? 2 : b - 1;    // slot of stage st + 2 (read last at stage st - 1)
-            if (st + 2 < nst) MOD_COPY(st + 2, b2);
+            // slot of stage st + kRing - 1, the one read last at stage st - 1
+            const int bn = b == 0 ? kRing - 1 : b - 1;
+            if (st + kRing - 1 < nst) MOD_COPY(st + kRing - 1, bn);
             const unsigned char *stage = smem + b * kStageBytes;
             const unsigned char *la = stage + (2 * wm) * kRunBytes + col * 16;
             const unsigned char *lb = stage + (8 + 2 * wn) * kRunBytes + col * 16;
@@ -321,12 +332,9 @@ __global__ __launch_bounds__(512, 1) void hs_mod_i8_kernel(const ModProblemDev *
                     }
                 }
             }
-            // stage st + 1 must have landed before anyone reads it; stage st + 2 may still fly
-            if (st + 1 < nst) {
-                if (st + 2 < nst) ring_barrier<6>();
-                else ring_barrier<0>();
-            }
-            b = b == 2 ? 0 : b + 1;
+            // stage st + 1 must have landed before anyone reads it; later stages may still fly
+            if (st + 1 < nst) ring_wait(min(kRing - 2, nst - st - 2));
+            b = b == kRing - 1 ? 0 : b + 1;
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
