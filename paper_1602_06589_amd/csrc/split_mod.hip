@@ -257,12 +257,12 @@ __global__ __launch_bounds__(512, 1) void hs_mod_i8_kernel(const ModProblemDev *
     // A stage is 12 runs (8 left, 4 right 32-column blocks) of kChunks 1 KB segments, 12 kChunks
     // segments in all.  Wave w copies segments g = w + 8q (run g / kChunks, chunk g % kChunks),
     // q = 0..kCopies-1, lane l's 16 bytes landing at +16 l; runs 0-7 come from the left operand
-    // exactly for q < kChunks.  Stages go round a ring of kRing buffers, kRing - 1 stages ahead.
+    // exactly for q < kChunks.  (The macro's own names end in '_' so that arguments cannot capture them.)  Stages go round a ring of kRing buffers, kRing - 1 stages ahead.
 #define MOD_COPY(st, b)                                                                           \
     do {                                                                                          \
-        _Pragma("unroll") for (int q = 0; q < kCopies; ++q) {                                     \
-            const int g_ = wave + 8 * q, r_ = g_ / kChunks, c_ = g_ % kChunks;                    \
-            const int8_t *src_ = (q < kChunks ? Lg + (long long)r_ * cbytes : Rg + (long long)(r_ - 8) * cbytes) + \
+        _Pragma("unroll") for (int cq_ = 0; cq_ < kCopies; ++cq_) {                               \
+            const int g_ = wave + 8 * cq_, r_ = g_ / kChunks, c_ = g_ % kChunks;                  \
+            const int8_t *src_ = (cq_ < kChunks ? Lg + (long long)r_ * cbytes : Rg + (long long)(r_ - 8) * cbytes) + \
                                  ((long long)(st) * kChunks + c_) * 1024 + lane * 16;             \
             __builtin_amdgcn_global_load_lds((const int __attribute__((address_space(1))) *)src_,   \
                 (int __attribute__((address_space(3))) *)(smem + (b) * kStageBytes + r_ * kRunBytes + c_ * 1024), \
@@ -272,8 +272,8 @@ __global__ __launch_bounds__(512, 1) void hs_mod_i8_kernel(const ModProblemDev *
 
     // stages 0 .. kRing - 2 in flight; wait for stage 0 (later stages may stay in flight)
 #pragma unroll
-    for (int q = 0; q + 1 < kRing; ++q)
-        if (q < nst) MOD_COPY(q, q);
+    for (int s0 = 0; s0 + 1 < kRing; ++s0)
+        if (s0 < nst) MOD_COPY(s0, s0);
     ring_wait(min(kRing - 2, nst - 1));
 
     const int half = lane >> 5, col = lane & 31;

@@ -106,8 +106,10 @@ def test_bf16_contract_random_operands(ctx, oracle_lib):
     assert _relfro(_upper(S.cpu().numpy()), So) < TOL_SPLIT
 
 
-def test_bf16_c1_sampled(ctx, oracle_lib):
-    cell = synthcells.config(1)
+@pytest.mark.parametrize("which", [1, 2])
+def test_bf16_sampled(ctx, oracle_lib, which):
+    """c1 (64 atoms) and the 256-atom precision workload c2, which names the bf16 variant."""
+    cell = synthcells.config(which)
     out = ctx.hs_generate(cell, cell.kpts, [_dev(g) for g in cell.gvecs], prec="bf16")
     T = oracle_lib.tmat_all(cell)
     H, S = out[0]

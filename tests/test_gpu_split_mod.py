@@ -165,3 +165,9 @@ def test_mod_c1_sampled(ctx, oracle_lib):
 def test_mod_c3_subset_sampled(ctx, oracle_lib):
     errs = _sampled(ctx, oracle_lib, synthcells.config(3, n_k=3), nsamp=32)
     assert max(errs) < TOL_SPLIT, errs
+
+
+def test_mod_c2_sampled(ctx, oracle_lib):
+    """The 256-atom precision workload (l_max 10, l'' 8, N = 6000) on sampled entries."""
+    errs = _sampled(ctx, oracle_lib, synthcells.config(2), nsamp=40)
+    assert max(errs) < TOL_SPLIT, errs
