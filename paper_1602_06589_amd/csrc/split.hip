@@ -224,8 +224,8 @@ __global__ __launch_bounds__(256, 1) void hs_split_i8_kernel(const SplitProblemD
     // and complete by the barrier that ends it (the barrier waits for all outstanding loads).
 #define SPLIT_COPY(st, b)                                                                       \
     do {                                                                                        \
-        _Pragma("unroll") for (int j = 0; j < kSegsPerWave; ++j) {                              \
-            const int sg_ = wave + 4 * j, run_ = sg_ / kRunSegs, off_ = (sg_ % kRunSegs) * 1024; \
+        _Pragma("unroll") for (int j_ = 0; j_ < kSegsPerWave; ++j_) {                              \
+            const int sg_ = wave + 4 * j_, run_ = sg_ / kRunSegs, off_ = (sg_ % kRunSegs) * 1024; \
             const int8_t *src_ = run_base[run_] + (long long)(st) * stage_step + off_ + lane * 16; \
             __builtin_amdgcn_global_load_lds((const int __attribute__((address_space(1))) *)src_, \
                 (int __attribute__((address_space(3))) *)(smem_raw + (b) * SM::kStageBytes + sg_ * 1024), 16, 0, 0); \
