@@ -1,7 +1,9 @@
 // FP64 matrix-core kernels of the contraction stage.
 //
-//  qpanel_kernel : Q_a = T_type(a) P_a for every atom (the paper's X_a, Z_a of sections 4.4-4.6,
-//                  here for the whole 2NL x 2NL block T at once), P_a = [A_a; B_a].
+//  qpanel_real_kernel : Q_a = T_type(a) P_a for every atom (the paper's X_a, Z_a of sections
+//                  4.4-4.6, here for the whole 2NL x 2NL block T at once), P_a = [A_a; B_a], for a
+//                  real T (the generation path: real radial integrals and Gaunt coefficients);
+//  qpanel_kernel : the same for a complex T supplied by the caller.
 //  hs_fp64_kernel: upper-triangle 64 x 64 tiles of
 //                    S = P^H D P   (D = 1 on A rows, ||udot_l||^2 on B rows; eq. def_overlap)
 //                    H = P^H Q     (eq. def_hamilton)
@@ -47,8 +49,7 @@ __device__ __forceinline__ v4d mfma(double a, double b, v4d c)
 // LDS panels are [column][k] complex; lane l reads row k = ks + l/16 of column base + l%16.
 // acc[y][0] = Re, acc[y][1] = Im.  The first sweep issues Xr.Yr and Xr.Yi for every block, the
 // second Xi.Yi and -Xi.Yr, so no two consecutive MFMAs use the same accumulator.
-// REAL_X: X has no imaginary part (the second sweep would add zeros and is skipped).
-template <int NY, int KS0 = 0, int KSTEP = 4, bool REAL_X = false>
+template <int NY, int KS0 = 0, int KSTEP = 4>
 __device__ __forceinline__ void stage_mma(const double2 (*X)[kSlot], const double2 (*Y0)[kSlot],
                                           const double2 (*Y1)[kSlot], int wm, int wn, int lane,
                                           v4d (&acc)[NY][2][2][2])
@@ -73,17 +74,15 @@ __device__ __forceinline__ void stage_mma(const double2 (*X)[kSlot], const doubl
                     acc[v][0][mi][ni] = mfma(x[mi].x, y[v][ni].x, acc[v][0][mi][ni]);
                     acc[v][1][mi][ni] = mfma(x[mi].x, y[v][ni].y, acc[v][1][mi][ni]);
                 }
-        if constexpr (!REAL_X) {
 #pragma unroll
-            for (int v = 0; v < NY; ++v)
+        for (int v = 0; v < NY; ++v)
 #pragma unroll
-                for (int mi = 0; mi < 2; ++mi)
+            for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-                    for (int ni = 0; ni < 2; ++ni) {
-                        acc[v][0][mi][ni] = mfma(x[mi].y, y[v][ni].y, acc[v][0][mi][ni]);
-                        acc[v][1][mi][ni] = mfma(-x[mi].y, y[v][ni].x, acc[v][1][mi][ni]);
-                    }
-        }
+                for (int ni = 0; ni < 2; ++ni) {
+                    acc[v][0][mi][ni] = mfma(x[mi].y, y[v][ni].y, acc[v][0][mi][ni]);
+                    acc[v][1][mi][ni] = mfma(-x[mi].y, y[v][ni].x, acc[v][1][mi][ni]);
+                }
     }
 }
 
@@ -229,10 +228,7 @@ struct QSmem {
     double2 v[2][2][kTile][kSlot];          // [buffer][X = T columns, Y = P rows of the atom][column][k]
 };
 
-// grid: x = column tile, y = atom, z = row tile of the atom's 2NL rows.
-// REAL_T: T has no imaginary part (T assembled from real radial integrals and real Gaunt
-// coefficients), so Re Q = T Re P and Im Q = T Im P take half the matrix-core work.
-template <bool REAL_T>
+// One block per (atom, 64-column tile, 64-row tile of the atom's 2NL rows); complex T.
 __global__ __launch_bounds__(kThreads, 1) void qpanel_kernel(const double2 *__restrict__ T, long long ldt,
                                                              long long tstride, const int *__restrict__ atom_type,
                                                              const int *__restrict__ atom_nl2,
@@ -307,7 +303,7 @@ __global__ __launch_bounds__(kThreads, 1) void qpanel_kernel(const double2 *__re
     for (int kt = 0; kt < nkt; ++kt) {
         const int b = kt & 1;
         if (kt + 1 < nkt) Q_LOAD(kt + 1);
-        stage_mma<1, 0, 4, REAL_T>(sm.v[b][0], sm.v[b][1], sm.v[b][1], wm, wn, lane, acc);
+        stage_mma<1>(sm.v[b][0], sm.v[b][1], sm.v[b][1], wm, wn, lane, acc);
         if (kt + 1 < nkt) Q_STORE(b ^ 1);
         __syncthreads();
     }
@@ -323,6 +319,137 @@ __global__ __launch_bounds__(kThreads, 1) void qpanel_kernel(const double2 *__re
                 const int row = r0 + wm + mi * 16 + (lane >> 4) + 4 * r;
                 const long long col = c0 + wn + ni * 16 + (lane & 15);
                 if (row < m2) Q[col * ldp + prow + row] = make_double2(acc[0][0][mi][ni][r], acc[0][1][mi][ni][r]);
+            }
+}
+
+constexpr int kQRows = 256;                 // rows of Q_a per block of the real-T kernel
+constexpr int kQThreads = 512;
+
+struct QRealSmem {
+    double x[2][kQRows][kSlot];             // [buffer][row of Q_a = column of T][k], Re T
+    double2 y[2][kTile][kSlot];             // [buffer][column of P_a][k]
+};
+
+// Real T: Re Q = T Re P and Im Q = T Im P, two real products per complex element.  One block per
+// unit (atom, 64-column tile, 256-row tile of the atom's 2NL rows; 2NL <= 256 needs one row tile),
+// so T is read once per 64 columns and P once in all.  Eight waves: wave w owns rows 64 (w >> 1)
+// and columns 32 (w & 1) of the 256 x 64 tile (4 x 2 MFMA blocks).  k-steps past the atom's
+// 2NL rows are skipped; rows past them are zero in LDS.  Units are listed atom-major and XCD x
+// (work-group b runs on XCD b mod 8) takes the x-th contiguous eighth of the list, so the column
+// tiles of one atom follow each other on one XCD and find T of its type in that XCD's L2.
+__global__ __launch_bounds__(kQThreads, 1) void qpanel_real_kernel(
+    const double2 *__restrict__ T, long long ldt, long long tstride, const int *__restrict__ atom_type,
+    const int *__restrict__ atom_nl2, const long long *__restrict__ atom_row, const double2 *__restrict__ P,
+    double2 *__restrict__ Q, long long ldp, int n_atoms, long long kp2, int n_ct, int row_tiles, long long per_xcd)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    QRealSmem &sm = *reinterpret_cast<QRealSmem *>(smem_raw);
+
+    const long long idx = blockIdx.x >> 3;
+    const long long u = (long long)(blockIdx.x & 7) * per_xcd + idx;
+    if (idx >= per_xcd || u >= (long long)(n_atoms + 1) * n_ct * row_tiles) return;
+    const int rt = (int)(u % row_tiles);
+    const long long v = u / row_tiles;
+    const int a = (int)(v / n_ct);
+    const long long c0 = (v % n_ct) * kTile;
+    if (a == n_atoms) {                                 // the padding rows of Q are zero, like P's
+        if (rt != 0) return;
+        const long long pad0 = atom_row[n_atoms - 1] + atom_nl2[n_atoms - 1];
+        const long long nr = kp2 - pad0;
+        for (long long i = threadIdx.x; i < nr * kTile; i += blockDim.x)
+            Q[(c0 + i / nr) * ldp + pad0 + i % nr] = make_double2(0.0, 0.0);
+        return;
+    }
+    const int m2 = atom_nl2[a];                         // 2 NL of this atom
+    const int r0 = rt * kQRows;
+    if (r0 >= m2) return;
+    const long long prow = atom_row[a];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 32;
+    const bool active = r0 + wm < m2;                   // the wave has rows of this atom
+    // loaders: lane group g = tid / 16 reads row lk = tid % 16 of a stage in T columns (tile rows)
+    // g + 32 j, j = 0..7, and in P columns g + 32 j, j = 0..1: 16 lanes cover one column's 256
+    // contiguous bytes.  Only the real part of T is kept.
+    const int lg = tid >> 4, lk = tid & 15;
+    gdouble2 *gX = (gdouble2 *)T + (long long)atom_type[a] * tstride + (long long)(r0 + lg) * ldt + lk;
+    gdouble2 *gY = (gdouble2 *)P + (c0 + lg) * ldp + prow + lk;
+
+    v4d acc[2][4][2];                                   // [re, im][mi][ni]
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n) acc[q][m][n] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+    double xv[8];
+    double2 yv[2];
+    auto load = [&](int kt) {
+        const int kb = kt * kKTile;
+        const bool k_ok = kb + lk < m2;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            xv[j] = 0.0;
+            if (k_ok && r0 + lg + 32 * j < m2) xv[j] = gX[32LL * j * ldt + kb].x;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            yv[j] = make_double2(0.0, 0.0);
+            if (k_ok) yv[j] = gY[32LL * j * ldp + kb];
+        }
+    };
+    auto store = [&](int b) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sm.x[b][lg + 32 * j][lk] = xv[j];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) sm.y[b][lg + 32 * j][lk] = yv[j];
+    };
+
+    const int nkt = (m2 + kKTile - 1) / kKTile;
+    const int c = lane & 15;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kt = 0; kt < nkt; ++kt) {
+        const int b = kt & 1;
+        if (kt + 1 < nkt) load(kt + 1);
+        if (active) {
+            const int kv = m2 - kt * kKTile;            // rows of this stage inside the atom
+#pragma unroll
+            for (int ks = 0; ks < kKTile; ks += 4) {
+                if (ks < kv) {
+                    const int k = ks + (lane >> 4);
+                    double xa[4];
+                    double2 yb[2];
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi) xa[mi] = sm.x[b][wm + mi * 16 + c][k];
+#pragma unroll
+                    for (int ni = 0; ni < 2; ++ni) yb[ni] = sm.y[b][wn + ni * 16 + c][k];
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni) {
+                            acc[0][mi][ni] = mfma(xa[mi], yb[ni].x, acc[0][mi][ni]);
+                            acc[1][mi][ni] = mfma(xa[mi], yb[ni].y, acc[1][mi][ni]);
+                        }
+                }
+            }
+        }
+        if (kt + 1 < nkt) store(b ^ 1);
+        __syncthreads();
+    }
+    if (!active) return;
+    // T is symmetric, so the product of its columns with P is T P.
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + wm + mi * 16 + (lane >> 4) + 4 * r;
+                const long long col = c0 + wn + ni * 16 + (lane & 15);
+                if (row < m2) Q[col * ldp + prow + row] = make_double2(acc[0][mi][ni][r], acc[1][mi][ni][r]);
             }
 }
 
@@ -355,11 +482,11 @@ hipError_t init_fp64_kernels()
         e = hipFuncSetAttribute((const void *)hs_fp64_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sizeof(HsSmem));
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)qpanel_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        e = hipFuncSetAttribute((const void *)qpanel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sizeof(QSmem));
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)qpanel_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sizeof(QSmem));
+        e = hipFuncSetAttribute((const void *)qpanel_real_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sizeof(QRealSmem));
     done = e;
     return e;
 }
@@ -381,20 +508,26 @@ hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, con
 {
     hipError_t e = init_fp64_kernels();
     if (e != hipSuccess) return e;
+    const int n_ct = np / kTile;
+    if (real_t) {
+        const int row_tiles = (int)((ldt + kQRows - 1) / kQRows);
+        const long long units = (long long)(n_atoms + 1) * n_ct * row_tiles;
+        const long long per_xcd = (units + 7) / 8;
+        if (8 * per_xcd > 0x7fffffffLL) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(qpanel_real_kernel, dim3((unsigned)(8 * per_xcd)), dim3(kQThreads), sizeof(QRealSmem), s, T,
+                           ldt, tstride, atom_type, atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2, n_ct, row_tiles,
+                           per_xcd);
+        return hipGetLastError();
+    }
     // row tiles: enough for the largest atom block (2 NL <= ldt)
     const int row_tiles = (int)((ldt + kTile - 1) / kTile);
-    const int n_ct = np / kTile;
     // units (atom, column tile), atom n_atoms zeroing the padding rows; 8 units per group of
     // 8 * row_tiles work-groups
     const long long units = (long long)(n_atoms + 1) * n_ct;
     const long long blocks = (units + 7) / 8 * 8 * row_tiles;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (real_t)
-        hipLaunchKernelGGL(qpanel_kernel<true>, dim3((unsigned)blocks), dim3(kThreads), sizeof(QSmem), s, T, ldt,
-                           tstride, atom_type, atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2, n_ct, row_tiles);
-    else
-        hipLaunchKernelGGL(qpanel_kernel<false>, dim3((unsigned)blocks), dim3(kThreads), sizeof(QSmem), s, T, ldt,
-                           tstride, atom_type, atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2, n_ct, row_tiles);
+    hipLaunchKernelGGL(qpanel_kernel, dim3((unsigned)blocks), dim3(kThreads), sizeof(QSmem), s, T, ldt, tstride,
+                       atom_type, atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2, n_ct, row_tiles);
     return hipGetLastError();
 }
 
