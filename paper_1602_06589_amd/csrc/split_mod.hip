@@ -163,21 +163,22 @@ __global__ __launch_bounds__(256) void mod_slice_kernel(const double2 *__restric
         write_residues(xr, mt, L + off, mstride);
         write_residues(xi, mt, L + off + 512, mstride);
     } else if (MODE == 0) {
-        double yr[16], yi[16];
-        const int e1 = eL[col], e2 = eRS[col];
+        // two passes over the 16 rows, residues of P then of d.P (w = 1 leaves P exact), so only
+        // one operand's values are live at a time; the second pass re-reads the rows from cache
+#pragma unroll 1
+        for (int ph = 0; ph < 2; ++ph) {
+            const int e = ph == 0 ? eL[col] : eRS[col];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const double2 v = col < np ? P[col * ld + r0 + r] : make_double2(0.0, 0.0);
-            const double w = d[r0 + r];
-            xr[r] = rint(ldexp(v.x, e1));
-            xi[r] = rint(ldexp(v.y, e1));
-            yr[r] = rint(ldexp(v.x * w, e2));
-            yi[r] = rint(ldexp(v.y * w, e2));
+            for (int r = 0; r < 16; ++r) {
+                const double2 v = col < np ? P[col * ld + r0 + r] : make_double2(0.0, 0.0);
+                const double w = ph == 0 ? 1.0 : d[r0 + r];
+                xr[r] = rint(ldexp(v.x * w, e));
+                xi[r] = rint(ldexp(v.y * w, e));
+            }
+            int8_t *o = ph == 0 ? L : RS;
+            write_residues(xr, mt, o + off, mstride);
+            write_residues(xi, mt, o + off + 512, mstride);
         }
-        write_residues(xr, mt, L + off, mstride);
-        write_residues(xi, mt, L + off + 512, mstride);
-        write_residues(yr, mt, RS + off, mstride);
-        write_residues(yi, mt, RS + off + 512, mstride);
     } else {
         const int e3 = eRH[col];
 #pragma unroll
