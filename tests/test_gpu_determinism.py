@@ -1,0 +1,67 @@
+"""Run-to-run determinism of the generation: the same inputs give bit-identical H and S on every
+call, for every precision and S method.
+
+Each output tile is accumulated by one work-group in a fixed order (FP64 partial sums, exact
+integer products, FP64 recombination), so any difference between two calls can only come from
+reading memory that was not yet written (an LDS stage used before its copy landed, a stale
+buffer).  Such a race leaves the results nondeterministic, and this test catches it whether or
+not the wrong values happen to stay within the oracle tolerance."""
+import numpy as np
+import pytest
+
+import synthcells
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_06589_amd import Flapw
+    f = Flapw()
+    yield f
+    f.close()
+
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+
+
+def _upper_bits(M):
+    """The upper triangle (column-major storage: row index <= column index) as raw 64-bit words."""
+    A = M.cpu().numpy()
+    n = A.shape[0]
+    up = np.triu(np.ones((n, n), bool)).T                 # entry [col][row] with row <= col
+    return A[up].view(np.uint64)
+
+
+def _twice(ctx, cell, prec, s_method):
+    g = [_dev(x) for x in cell.gvecs]
+    ctx.set_s_method(s_method)
+    try:
+        first = [(_upper_bits(H), _upper_bits(S)) for H, S in ctx.hs_generate(cell, cell.kpts, g, prec=prec)]
+        second = [(_upper_bits(H), _upper_bits(S)) for H, S in ctx.hs_generate(cell, cell.kpts, g, prec=prec)]
+    finally:
+        ctx.set_s_method("gemm")
+    return first, second
+
+
+@pytest.mark.parametrize("s_method", ["gemm", "legendre"])
+@pytest.mark.parametrize("prec", ["fp64", "i8", "bf16", "i8mod"])
+def test_c1_bit_identical(ctx, prec, s_method):
+    print(f"determinism c1 {prec} {s_method}", flush=True)
+    first, second = _twice(ctx, synthcells.config(1), prec, s_method)
+    for (h1, s1), (h2, s2) in zip(first, second):
+        assert np.array_equal(h1, h2), "H differs between two identical calls"
+        assert np.array_equal(s1, s2), "S differs between two identical calls"
+
+
+def test_c2_modular_bit_identical(ctx):
+    """256 atoms: 968 stages of 64 rows, two flush periods of the modular contraction."""
+    print("determinism c2 i8mod gemm", flush=True)
+    first, second = _twice(ctx, synthcells.config(2), "i8mod", "gemm")
+    for (h1, s1), (h2, s2) in zip(first, second):
+        assert np.array_equal(h1, h2) and np.array_equal(s1, s2)
