@@ -3,11 +3,14 @@
 one MI355X, for the seeded synthetic workloads of synthcells.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--precs i8mod,i8,fp64,i8mod+leg,fp64+leg]
-                    [--slices s]
+                    [--slices s | --no-tune]
 
 A path is a precision (i8mod, i8, bf16 or fp64 for the S/H contraction) with an optional "+leg": S then
 comes from the addition theorem (section 3.1) and the contraction computes H alone.  The first
 path is the headline.
+Before its timing, each split path runs the library's autotuner on k-point 0 (flapw_tune: the
+smallest digit or modulus count whose H and S errors on a sampled block are at most 1e-10 / 4,
+then the fastest tile band); --slices fixes the count instead and --no-tune takes the defaults.
 A step is one flapw_hs_generate call over every k-point of the workload (the whole path).
 Inputs (G lists) are resident in HBM before timing starts; K timed steps are bracketed by
 torch.cuda.synchronize().  Prints one JSON line:
@@ -167,8 +170,10 @@ def main():
     ap.add_argument("--no-ceiling", action="store_true", help="skip the matrix-core rate microbenchmark")
     ap.add_argument("--graph", action="store_true",
                     help="also time replays of the generation captured in a HIP graph (flapw_plan_*)")
-    ap.add_argument("--tune", action="store_true",
-                    help="run the autotuner (digit count at 1e-10, tile band) on k-point 0 before timing")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner and use the library's default digit or modulus count and tile "
+                         "band (by default each split path is tuned on k-point 0 before timing: the smallest "
+                         "count whose sampled error is at most 1e-10 / 4, then the fastest band)")
     ap.add_argument("--cpu-sample", type=int, default=384)
     ap.add_argument("--radial-nr", type=int, default=1001,
                     help="mesh points of the radial-setup leg (radial functions and integrals of the "
@@ -232,7 +237,7 @@ def main():
             fl.set_s_method(s_method)
             fl.set_lnonsph(args.lnonsph)
             tuned = None
-            if args.tune:
+            if not args.no_tune and prec != "fp64" and not args.slices:
                 t0 = time.perf_counter()
                 tuned = fl.tune(cell, cell.kpts[0], gdev[0], prec=prec, tol=1e-10)
                 tuned["seconds"] = time.perf_counter() - t0

@@ -74,7 +74,7 @@ typedef enum {
  *               2-norm is below 2^B and rounded to integers; the exact integer products are
  *               computed modulo `slices` pairwise coprime odd moduli <= 255 (one int8 matrix-core
  *               product per modulus, int32 accumulation) and rebuilt by the Chinese remainder
- *               theorem in FP64 (B = min(50, floor((log2 M - 3)/2)), M the product of the
+ *               theorem in FP64 (B = min(50, floor((log2 M - 1)/2)), M the product of the
  *               moduli).  Takes 8..14 moduli (FLAPW_ERR_UNSUPPORTED for 1..7); 0 selects the
  *               tuned or default count (11).  Needs, per k-point in flight, 2 `slices` bytes per
  *               element of each of three 2K x N operands plus 64 `slices` KiB per 128 x 128

@@ -55,7 +55,7 @@ def _bits(nm):
         if all(math.gcd(c, m) == 1 for m in mods):
             mods.append(c)
         c -= 2
-    return min(50, int(math.floor((sum(math.log2(m) for m in mods) - 3) / 2)))
+    return min(50, int(math.floor((sum(math.log2(m) for m in mods) - 1) / 2)))
 
 
 def _full_errors(ctx, oracle_lib, cell, slices=0):
