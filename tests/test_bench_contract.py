@@ -1,0 +1,62 @@
+"""bench.py host logic, on the CPU: the refusal of more than one GPU, the refusal without a GPU,
+the counter-summary lookup that fills the roofline's traffic (and its invalidation when the
+kernel source changes), and the executed-operation factors of the split paths."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                          timeout=300, cwd=ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _run("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_no_gpu_is_an_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    r = _run("--steps", "1", "--warmup", "0")
+    assert r.returncode == 1
+    assert "no GPU" in r.stderr
+
+
+def test_source_hash_is_the_kernel_file_hash():
+    path = os.path.join(ROOT, "paper_1602_06589_amd", "csrc", "split_mod.hip")
+    with open(path, "rb") as f:
+        assert bench.kernel_sources_sha("i8mod") == hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def test_traffic_line_is_read_for_the_current_source(tmp_path, monkeypatch):
+    sha = bench.kernel_sources_sha("i8mod")
+    p = tmp_path / "traffic.txt"
+    p.write_text("notes\n"
+                 f"traffic kernel=hs_mod workload=c4_scale src_sha={sha} bytes_per_launch=123000\n"
+                 "traffic kernel=hs_mod workload=c1_realistic src_sha=0000000000000000 bytes_per_launch=7\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
+    assert bench.read_traffic("i8mod", "c4_scale") == 123000.0
+    # a line recorded for another source version is ignored
+    assert bench.read_traffic("i8mod", "c1_realistic") is None
+    # other kernels and workloads without a line
+    assert bench.read_traffic("fp64", "c4_scale") is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.read_traffic("i8mod", "c4_scale") is None
+
+
+@pytest.mark.parametrize("prec,slices,factor", [("i8mod", 10, 10.0), ("i8mod", 11, 11.0), ("i8", 6, 21.0),
+                                                ("bf16", 6, 21.0), ("i8", 3, 6.0)])
+def test_executed_operations_per_flop(prec, slices, factor):
+    """One int8 product per modulus; s(s+1)/2 digit-pair products for the digit schemes."""
+    assert bench.executed_per_flop(slices, prec) == factor
