@@ -7,10 +7,11 @@
 // Integers.  Operand column c (a basis function) is scaled by 2^e_c, e_c chosen so that the
 // 2-norm of the column over all contraction rows (real and imaginary parts) is below 2^B, and
 // rounded: X'_kc = rint(X_kc 2^e_c), |X'| < 2^B <= 2^50 (exact in FP64).  By Cauchy-Schwarz every
-// exact integer product entry C'_ij = Re or Im of sum_k conj(X'_ki) Y'_kj has |C'| < 2^(2B) (to a
-// relative 2^-32 for the rounding of X' and Y'), and B is the largest with 2^(2B+1) <= M = prod p_m;
-// for 8..14 moduli log2 M exceeds 2B + 1 by at least 0.04, so |C'| < 0.49 M and C' is the unique
-// residue of C' mod M in (-M/2, M/2).
+// exact integer product entry C'_ij = Re or Im of sum_k conj(X'_ki) Y'_kj has |C'| < 2^(2B) up to
+// the rounding of X' and Y' (each adds at most sqrt(2K)/2 < 2^15 to a column norm below 2^B, B >= 31,
+// so a factor below 1 + 2^-15 in all), and B is the largest with 2^(2B+1) <= M = prod p_m; for 8..14
+// moduli log2 M exceeds 2B + 1 by at least 0.04 (a factor 1.028), so |C'| < 0.49 M and C' is the
+// unique residue of C' mod M in (-M/2, M/2).
 //
 // Residues.  r = X' mod p_m in the symmetric range [-(p-1)/2, (p-1)/2] fits int8; the moduli are
 // odd so that -128 never occurs and the packed byte negation below never carries into the next
