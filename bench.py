@@ -206,6 +206,7 @@ def main():
     import torch
     import synthcells
     from paper_1602_06589_amd import Flapw
+    from paper_1602_06589_amd.flapw import FlapwError
 
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
@@ -239,7 +240,10 @@ def main():
             tuned = None
             if not args.no_tune and prec != "fp64" and not args.slices:
                 t0 = time.perf_counter()
-                tuned = fl.tune(cell, cell.kpts[0], gdev[0], prec=prec, tol=1e-10)
+                try:
+                    tuned = fl.tune(cell, cell.kpts[0], gdev[0], prec=prec, tol=1e-10)
+                except FlapwError as err:         # no candidate count meets the tolerance
+                    tuned = {"error": str(err)}
                 tuned["seconds"] = time.perf_counter() - t0
                 print(f"# {path}: tuned {json.dumps(tuned)}", flush=True)
             out = [(torch.zeros((cell.n_g(i), cell.n_g(i)), dtype=torch.complex128, device="cuda"),
