@@ -882,7 +882,8 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
                 ProfScope prof(h, "qpanel", s);
                 e = launch_qpanel(p.T, p.ldt, p.ldt * p.ldt, (const int *)(p.tables + p.oty),
                                   (const int *)(p.tables + p.onl), (const long long *)(p.tables + p.orow), p.n_atoms, P,
-                                  Q, L.kp2, (int)p.np[i], L.kp2, true, s);
+                                  Q, L.kp2, (int)p.np[i], L.kp2, true,
+                                  *std::min_element(L.atom_nl2.begin(), L.atom_nl2.end()), s);
             }
             if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
             if (p.split) {
@@ -1288,7 +1289,7 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
     {
         ProfScope prof(h, "qpanel", s);
         e = launch_qpanel((const double2 *)T, ldt, ldt * ldt, (const int *)(base + oty), (const int *)(base + onl),
-                          (const long long *)(base + orow), at->n_atoms, P, Q, L.kp2, (int)np, L.kp2, false, s);
+                          (const long long *)(base + orow), at->n_atoms, P, Q, L.kp2, (int)np, L.kp2, false, 0, s);
     }
     if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
     ProblemDev pd{P, Q, (const double *)(base + od), (double2 *)H, (double2 *)S, L.kp2, ldh, n_g, (int)L.kp2};

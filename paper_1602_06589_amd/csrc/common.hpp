@@ -93,7 +93,7 @@ hipError_t launch_tmat(int n_types, const int *lmax_dev, int lstride, int lpot, 
 // to zero.  real_t: T is known to be real (built by the library from real integrals): half the MFMAs
 hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, const int *atom_type, const int *atom_nl2,
                          const long long *atom_row, int n_atoms, const double2 *P, double2 *Q, long long ldp, int np,
-                         long long kp2, bool real_t, hipStream_t s);
+                         long long kp2, bool real_t, int min_nl2, hipStream_t s);
 
 // with_s = false: H alone (S tiles of the problems are not touched)
 hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_tiles, bool with_s, hipStream_t s);

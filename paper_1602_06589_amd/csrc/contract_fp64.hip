@@ -332,11 +332,16 @@ struct QRealSmem {
 
 // Real T: Re Q = T Re P and Im Q = T Im P, two real products per complex element.  One block per
 // unit (atom, 64-column tile, 256-row tile of the atom's 2NL rows; 2NL <= 256 needs one row tile),
-// so T is read once per 64 columns and P once in all.  Eight waves: wave w owns rows 64 (w >> 1)
-// and columns 32 (w & 1) of the 256 x 64 tile (4 x 2 MFMA blocks).  k-steps past the atom's
-// 2NL rows are skipped; rows past them are zero in LDS.  Units are listed atom-major and XCD x
+// so T is read once per 64 columns and P once in all.  Eight waves: wave w owns the 16-row blocks
+// (w >> 1) + 4 i, i = 0..3, and columns 32 (w & 1) of the 256 x 64 tile (4 x 2 MFMA blocks); row
+// blocks are dealt round-robin so that an atom with fewer rows (2NL = 162 at l_max 8) still keeps
+// every wave busy, and row blocks past 2NL are skipped, as are k-steps past 2NL (rows past them
+// are zero in LDS).  Units are listed atom-major and XCD x
 // (work-group b runs on XCD b mod 8) takes the x-th contiguous eighth of the list, so the column
 // tiles of one atom follow each other on one XCD and find T of its type in that XCD's L2.
+// FULL: every atom of the launch has 2NL > 240 and one row tile, so every row block of every wave
+// holds rows and the per-block tests (which cost a few per cent) compile away.
+template <bool FULL>
 __global__ __launch_bounds__(kQThreads, 1) void qpanel_real_kernel(
     const double2 *__restrict__ T, long long ldt, long long tstride, const int *__restrict__ atom_type,
     const int *__restrict__ atom_nl2, const long long *__restrict__ atom_row, const double2 *__restrict__ P,
@@ -366,8 +371,11 @@ __global__ __launch_bounds__(kQThreads, 1) void qpanel_real_kernel(
     const long long prow = atom_row[a];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 32;
-    const bool active = r0 + wm < m2;                   // the wave has rows of this atom
+    const int wr = wave >> 1, wn = (wave & 1) * 32;
+    bool act[4];                                        // row block wr + 4 i holds rows of this atom
+#pragma unroll
+    for (int i = 0; i < 4; ++i) act[i] = FULL || r0 + (wr + 4 * i) * 16 < m2;
+    const bool active = act[0];
     // loaders: lane group g = tid / 16 reads row lk = tid % 16 of a stage in T columns (tile rows)
     // g + 32 j, j = 0..7, and in P columns g + 32 j, j = 0..1: 16 lanes cover one column's 256
     // contiguous bytes.  Only the real part of T is kept.
@@ -423,15 +431,17 @@ __global__ __launch_bounds__(kQThreads, 1) void qpanel_real_kernel(
                     double xa[4];
                     double2 yb[2];
 #pragma unroll
-                    for (int mi = 0; mi < 4; ++mi) xa[mi] = sm.x[b][wm + mi * 16 + c][k];
+                    for (int mi = 0; mi < 4; ++mi) xa[mi] = act[mi] ? sm.x[b][(wr + 4 * mi) * 16 + c][k] : 0.0;
 #pragma unroll
                     for (int ni = 0; ni < 2; ++ni) yb[ni] = sm.y[b][wn + ni * 16 + c][k];
 #pragma unroll
                     for (int mi = 0; mi < 4; ++mi)
+                        if (act[mi]) {
 #pragma unroll
-                        for (int ni = 0; ni < 2; ++ni) {
-                            acc[0][mi][ni] = mfma(xa[mi], yb[ni].x, acc[0][mi][ni]);
-                            acc[1][mi][ni] = mfma(xa[mi], yb[ni].y, acc[1][mi][ni]);
+                            for (int ni = 0; ni < 2; ++ni) {
+                                acc[0][mi][ni] = mfma(xa[mi], yb[ni].x, acc[0][mi][ni]);
+                                acc[1][mi][ni] = mfma(xa[mi], yb[ni].y, acc[1][mi][ni]);
+                            }
                         }
                 }
             }
@@ -447,7 +457,7 @@ __global__ __launch_bounds__(kQThreads, 1) void qpanel_real_kernel(
         for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = r0 + wm + mi * 16 + (lane >> 4) + 4 * r;
+                const int row = r0 + (wr + 4 * mi) * 16 + (lane >> 4) + 4 * r;
                 const long long col = c0 + wn + ni * 16 + (lane & 15);
                 if (row < m2) Q[col * ldp + prow + row] = make_double2(acc[0][mi][ni][r], acc[1][mi][ni][r]);
             }
@@ -485,7 +495,10 @@ hipError_t init_fp64_kernels()
         e = hipFuncSetAttribute((const void *)qpanel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sizeof(QSmem));
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)qpanel_real_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+        e = hipFuncSetAttribute((const void *)qpanel_real_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sizeof(QRealSmem));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)qpanel_real_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sizeof(QRealSmem));
     done = e;
     return e;
@@ -504,7 +517,7 @@ hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_t
 
 hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, const int *atom_type, const int *atom_nl2,
                          const long long *atom_row, int n_atoms, const double2 *P, double2 *Q, long long ldp, int np,
-                         long long kp2, bool real_t, hipStream_t s)
+                         long long kp2, bool real_t, int min_nl2, hipStream_t s)
 {
     hipError_t e = init_fp64_kernels();
     if (e != hipSuccess) return e;
@@ -514,9 +527,14 @@ hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, con
         const long long units = (long long)(n_atoms + 1) * n_ct * row_tiles;
         const long long per_xcd = (units + 7) / 8;
         if (8 * per_xcd > 0x7fffffffLL) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(qpanel_real_kernel, dim3((unsigned)(8 * per_xcd)), dim3(kQThreads), sizeof(QRealSmem), s, T,
-                           ldt, tstride, atom_type, atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2, n_ct, row_tiles,
-                           per_xcd);
+        if (row_tiles == 1 && min_nl2 > kQRows - 16)
+            hipLaunchKernelGGL(qpanel_real_kernel<true>, dim3((unsigned)(8 * per_xcd)), dim3(kQThreads), sizeof(QRealSmem),
+                               s, T, ldt, tstride, atom_type, atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2, n_ct, row_tiles,
+                               per_xcd);
+        else
+            hipLaunchKernelGGL(qpanel_real_kernel<false>, dim3((unsigned)(8 * per_xcd)), dim3(kQThreads), sizeof(QRealSmem),
+                               s, T, ldt, tstride, atom_type, atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2, n_ct, row_tiles,
+                               per_xcd);
         return hipGetLastError();
     }
     // row tiles: enough for the largest atom block (2 NL <= ldt)
