@@ -1,6 +1,6 @@
 """Edge cases of the whole path on the GPU, every precision and both S methods, against the
 oracle: one basis function, exactly one tile and one tile plus one column, a single atom with
-l_max and l''_max at the library caps, and the largest workload (c4_scale, k-point 0, in the
+l_max and l''_max at the library caps, the Gamma point (K = 0 in the basis), and the largest workload (c4_scale, k-point 0, in the
 configuration the benchmark times) on sampled entries."""
 import numpy as np
 import pytest
@@ -71,6 +71,17 @@ def test_tile_edges(handles, oracle_lib, n_g, prec, method):
 def test_caps_single_atom(handles, oracle_lib, prec, method):
     """One atom, l_max = 12 (2 NL = 338 rows) and l''_max = 12."""
     cell = _cell(230, types=(0,), lmax=(12,), lpot=12, seed=8, a=7.0)
+    _check_full(handles, oracle_lib, cell, prec, method)
+
+
+@pytest.mark.parametrize("method", ["gemm", "legendre"])
+@pytest.mark.parametrize("prec", ["fp64", "i8", "bf16", "i8mod"])
+def test_gamma_point(handles, oracle_lib, prec, method):
+    """k = 0: the basis includes K = 0, whose direction is undefined (only l = 0 survives there)."""
+    rng = np.random.default_rng(13)
+    cell = synthcells.custom_cell("gamma", 9.0, rng.uniform(0, 9.0, size=(3, 3)), np.array([0, 1, 0], np.int32),
+                                  [5, 3], [1.7, 1.9], 4, 97, [13], kpts=np.zeros((1, 3)), rotations="random")
+    assert np.min(np.linalg.norm(cell.gvecs[0], axis=1)) == 0.0
     _check_full(handles, oracle_lib, cell, prec, method)
 
 
