@@ -1,8 +1,8 @@
 """Edge cases of the whole path on the GPU, every precision and both S methods, against the
 oracle: one basis function, exactly one tile and one tile plus one column, a single atom with
 l_max and l''_max at the library caps, the Gamma point (K = 0 in the basis), and the largest
-workload (c4_scale: k-point 0 in every precision, all four k-points through the modular path in
-the configuration the benchmark times) on sampled entries."""
+workload (c4_scale, k-point 0, in the configuration the benchmark times) on sampled entries.  All
+four k-points of that workload: test_gpu_c4_batches.py."""
 import numpy as np
 import pytest
 
@@ -110,26 +110,3 @@ def test_c4_kpoint0_sampled(handles, oracle_lib):
                 err = float(np.linalg.norm((got - ref)[up]) / np.linalg.norm(ref[up]))
                 tol = 1e-12 if (prec == "fp64" or (name == "S" and method == "legendre")) else 1e-10
                 assert err < tol, (method, prec, slices, name, err)
-
-
-def test_c4_all_kpoints_modular_sampled(handles, oracle_lib):
-    """All four k-points of the largest workload through the modular path (10 moduli, the
-    benchmark's count): one memory batch per k-point, so batches after the first reuse the
-    residue and panel buffers.  24 sampled basis functions per k-point against the oracle."""
-    cell = synthcells.config(4)
-    g = [_dev(x) for x in cell.gvecs]
-    out = handles["gemm"].hs_generate(cell, cell.kpts, g, prec="i8mod", slices=10)
-    T = oracle_lib.tmat_all(cell)
-    for ik, (H, S) in enumerate(out):
-        n = cell.n_g(ik)
-        rng = np.random.default_rng(500 + ik)
-        idx = np.unique(np.concatenate([rng.choice(n, 24, replace=False), [0, n - 1]]))
-        print(f"c4 k-point {ik} sampled: i8mod 10 moduli", flush=True)
-        Ho, So = oracle_lib.hs_sampled(cell, ik, idx, idx, T)
-        sub_idx = _dev(idx)
-        Hs = H[sub_idx][:, sub_idx].cpu().numpy().T
-        Ss = S[sub_idx][:, sub_idx].cpu().numpy().T
-        up = idx[:, None] <= idx[None, :]
-        for name, got, ref in (("H", Hs, Ho), ("S", Ss, So)):
-            err = float(np.linalg.norm((got - ref)[up]) / np.linalg.norm(ref[up]))
-            assert err < 1e-10, (ik, name, err)
