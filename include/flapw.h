@@ -134,6 +134,11 @@ const char *flapw_status_string(flapw_status s);
 const char *flapw_last_error(flapw_handle h);
 /* Device memory held by the handle's work buffers, in bytes. */
 long long flapw_workspace_bytes(flapw_handle h);
+/* Frees the handle's work buffers.  They grow to the largest call made so far (about 100 GB for
+ * a 512-atom k-point in the modular split precision) and are allocated again by the next call
+ * that needs them; nothing in them outlives a call.  Waits for the device first, as
+ * flapw_destroy does; plans keep their own buffers.  Errors: FLAPW_ERR_ARG for a NULL handle. */
+flapw_status flapw_release_workspace(flapw_handle h);
 
 /* Matching coefficients A_* and B_* of one k-point (appendix A.1, eqs. def_a_tensor,
  * def_b_tensor; Wronskian W = udot u' - u udot'; stacked layout of section 4.2).

@@ -1185,6 +1185,21 @@ flapw_status flapw_profile_query(flapw_handle h, const char *family, int *launch
     return FLAPW_OK;
 }
 
+flapw_status flapw_release_workspace(flapw_handle h)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    if (h->device >= 0) (void)hipDeviceSynchronize();
+    h->work.release();
+    h->tmat.release();
+    h->tables.release();
+    h->gaunt.release();
+    h->tiles.release();
+    h->leg.release();
+    h->radial.release();
+    split_release(h);
+    return FLAPW_OK;
+}
+
 long long flapw_workspace_bytes(flapw_handle h)
 {
     if (!h) return -1;

@@ -34,6 +34,7 @@ _STATUS = {0: "FLAPW_OK", -1: "FLAPW_ERR_ARG", -2: "FLAPW_ERR_WRONSKIAN", -3: "F
            -4: "FLAPW_ERR_NOMEM", -5: "FLAPW_ERR_DEVICE", -6: "FLAPW_ERR_UNSUPPORTED"}
 
 EXPORTS = ["flapw_create", "flapw_destroy", "flapw_status_string", "flapw_last_error", "flapw_workspace_bytes",
+           "flapw_release_workspace",
            "flapw_coeffs", "flapw_build_T", "flapw_hs_contract", "flapw_hs_generate", "flapw_set_s_method",
            "flapw_set_lnonsph", "flapw_s_legendre", "flapw_plan_create",
            "flapw_plan_launch", "flapw_plan_destroy", "flapw_tune", "flapw_profile_enable", "flapw_profile_query",
@@ -89,6 +90,8 @@ def load_library(path: str = LIB_PATH):
         lib.flapw_last_error.restype = ctypes.c_char_p
         lib.flapw_workspace_bytes.argtypes = [P]
         lib.flapw_workspace_bytes.restype = ctypes.c_longlong
+        lib.flapw_release_workspace.argtypes = [P]
+        lib.flapw_release_workspace.restype = ctypes.c_int
         lib.flapw_coeffs.argtypes = [P, P, I, P, P, P, P, P, L, P]
         lib.flapw_build_T.argtypes = [P, P, P, P, L, P]
         lib.flapw_hs_contract.argtypes = [P, I, P, P, P, P, L, P, L, P, P, L, I, I, P]
@@ -190,6 +193,10 @@ class Flapw:
     @property
     def workspace_bytes(self) -> int:
         return int(self._lib.flapw_workspace_bytes(self._h))
+
+    def release_workspace(self):
+        """Free the handle's work buffers (the next call allocates what it needs again)."""
+        self._check(self._lib.flapw_release_workspace(self._h))
 
     # --------------------------------------------------------------------- descriptors
     def _radial(self, s):

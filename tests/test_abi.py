@@ -285,3 +285,12 @@ def test_radial_setup_validation(handle):
 def _has_device():
     import torch
     return torch.cuda.device_count() > 0
+
+
+def test_release_workspace(handle, lib):
+    """Releasing the work buffers of a handle leaves it usable and holding nothing; a NULL handle
+    is an argument error."""
+    handle.release_workspace()
+    assert handle.workspace_bytes == 0
+    handle.release_workspace()
+    assert lib.flapw_release_workspace(None) == -1

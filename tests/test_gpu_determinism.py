@@ -65,3 +65,18 @@ def test_c2_modular_bit_identical(ctx):
     first, second = _twice(ctx, synthcells.config(2), "i8mod", "gemm")
     for (h1, s1), (h2, s2) in zip(first, second):
         assert np.array_equal(h1, h2) and np.array_equal(s1, s2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "i8mod"])
+def test_release_workspace_between_calls(ctx, prec):
+    """Freeing the handle's work buffers between two identical calls changes nothing: the second
+    call allocates them again and returns the same bits."""
+    cell = synthcells.config(1)
+    g = [_dev(x) for x in cell.gvecs]
+    first = [(_upper_bits(H), _upper_bits(S)) for H, S in ctx.hs_generate(cell, cell.kpts, g, prec=prec)]
+    assert ctx.workspace_bytes > 0
+    ctx.release_workspace()
+    assert ctx.workspace_bytes == 0
+    second = [(_upper_bits(H), _upper_bits(S)) for H, S in ctx.hs_generate(cell, cell.kpts, g, prec=prec)]
+    for (h1, s1), (h2, s2) in zip(first, second):
+        assert np.array_equal(h1, h2) and np.array_equal(s1, s2)
