@@ -739,6 +739,12 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     for (int i = 0; i < n_k; ++i) np_max = std::max(np_max, p.np[i]);
     const size_t panel_one = (size_t)2 * L.kp2 * np_max * sizeof(double2);
     size_t budget = (size_t)(frac * (double)total_b);
+    // never more than the device holds now: free memory plus this call's own work and digit
+    // buffers, which are freed and allocated again when they must grow (10 % held back for the
+    // rest); other handles and the caller's tensors then only make the batches smaller, which
+    // leaves the results unchanged
+    const size_t avail = free_b + b.work->n + (p.split ? b.digits->n : 0);
+    budget = std::min(budget, (size_t)(0.9 * (double)avail));
     if (p.split) budget = budget > panel_one ? budget - panel_one : 0;
     std::vector<size_t> need(n_k);
     for (int i = 0; i < n_k; ++i)
