@@ -1,6 +1,6 @@
 """Edge cases of the whole path on the GPU, every precision and both S methods, against the
 oracle: one basis function, exactly one tile and one tile plus one column, a single atom with
-l_max and l''_max at the library caps, the Gamma point (K = 0 in the basis), and the largest
+l_max and l''_max at the library caps, atoms with l_max 0 and 1, the Gamma point (K = 0 in the basis), and the largest
 workload (c4_scale, k-point 0, in the configuration the benchmark times) on sampled entries.  All
 four k-points of that workload: test_gpu_c4_batches.py."""
 import numpy as np
@@ -72,6 +72,14 @@ def test_tile_edges(handles, oracle_lib, n_g, prec, method):
 def test_caps_single_atom(handles, oracle_lib, prec, method):
     """One atom, l_max = 12 (2 NL = 338 rows) and l''_max = 12."""
     cell = _cell(230, types=(0,), lmax=(12,), lpot=12, seed=8, a=7.0)
+    _check_full(handles, oracle_lib, cell, prec, method)
+
+
+@pytest.mark.parametrize("method", ["gemm", "legendre"])
+@pytest.mark.parametrize("prec", ["fp64", "i8", "bf16", "i8mod"])
+def test_smallest_lmax(handles, oracle_lib, prec, method):
+    """Atoms with l_max 0 and 1 (2NL = 2 and 8 rows): most Q-panel waves hold no rows."""
+    cell = _cell(150, types=(0, 1, 1, 0), lmax=(0, 1), lpot=2, seed=17)
     _check_full(handles, oracle_lib, cell, prec, method)
 
 
