@@ -1,5 +1,5 @@
 """Edge cases of the whole path on the GPU, every precision and both S methods, against the
-oracle: one basis function, exactly one tile and one tile plus one column, a single atom with
+oracle: one basis function, exactly one tile and one tile plus one column (64, 128, 256), a single atom with
 l_max and l''_max at the library caps, atoms with l_max 0 and 1, the Gamma point (K = 0 in the basis), and the largest
 workload (c4_scale, k-point 0, in the configuration the benchmark times) on sampled entries.  All
 four k-points of that workload: test_gpu_c4_batches.py."""
@@ -62,8 +62,10 @@ def _check_full(handles, oracle_lib, cell, prec, method):
 
 @pytest.mark.parametrize("method", ["gemm", "legendre"])
 @pytest.mark.parametrize("prec", ["fp64", "i8", "bf16", "i8mod"])
-@pytest.mark.parametrize("n_g", [1, 64, 65])
+@pytest.mark.parametrize("n_g", [1, 64, 65, 128, 129, 256, 257])
 def test_tile_edges(handles, oracle_lib, n_g, prec, method):
+    """Tile boundaries: 64 (FP64 and digit tiles), 128 (modular reconstruction tiles) and 256
+    (modular contraction blocks), each exactly and plus one column."""
     _check_full(handles, oracle_lib, _cell(n_g), prec, method)
 
 
