@@ -58,14 +58,14 @@ static_assert(kChunks % 2 == 0 && kRing >= 2 && kRing <= 4 && (kRing - 2) * kCop
 constexpr int kFlushStages = 32768 / kStageRows;  // 32768 rows * 2 * 127^2 < 2^31
 constexpr int kResTileBytes = kModTile * kModTile * 2;  // int8 residues of Re and Im
 
-// x mod p in [-(p-1)/2, (p-1)/2] for odd p and integer-valued |x| < 2^52
+// x mod p in [-(p-1)/2, (p-1)/2] for odd p, ip = fl(1/p) and integer-valued |x| <= 2^50 (1 + 2^-15).
+// x/p lies at least 1/(2p) from the nearest half-integer (x is an integer and p is odd), and the
+// two roundings in fl(x ip) move it by at most about |x|/p 2^-52 <= 1.0001/(4p), so rint returns the nearest
+// quotient, the remainder from the fma is exact and already in the symmetric range.
 __device__ inline int sym_mod(double x, double p, double ip)
 {
     const double q = rint(x * ip);
-    double r = fma(-q, p, x);
-    if (r > 0.5 * (p - 1.0)) r -= p;
-    else if (r < -0.5 * (p - 1.0)) r += p;
-    return (int)r;
+    return (int)fma(-q, p, x);
 }
 
 // int32 reduction mod odd p in 32-bit arithmetic.  One step leaves |r| <= 3p for any int32 x
@@ -138,7 +138,9 @@ __device__ inline void write_residues(const double (&v)[16], const ModTable &mt,
 
 // grid (npm/32, kp2/128): thread (m = tid % 32, chunk = tid / 32) handles 16 rows of column
 // 32 blockIdx.x + m.  MODE 0: residues of P (left) and d.P (right of S); MODE 1: of Q (right of H);
-// MODE 2: of P alone (S is not contracted).
+// MODE 2: of P alone (S is not contracted).  The 16 values are read once and each operand (its real
+// parts, then its imaginary parts) is formed and reduced in turn, so that one operand's 16 integers
+// are live beside them.
 template <int MODE>
 __global__ __launch_bounds__(256) void mod_slice_kernel(const double2 *__restrict__ P, const double2 *__restrict__ Q,
                                                         const double *__restrict__ d, long long ld, int kp2, int np,
@@ -154,44 +156,48 @@ __global__ __launch_bounds__(256) void mod_slice_kernel(const double2 *__restric
     const long long mstride = ncb * nch * 1024;
     const long long off = (cb * nch + ch) * 1024 + m * 16;
     const long long r0 = ch * 16;
-    double xr[16], xi[16];
+    double xr[16];
     if (MODE == 2) {
-        const int e1 = eL[col];
+        const int ex = eL[col];
+        double2 v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const double2 v = col < np ? P[col * ld + r0 + r] : make_double2(0.0, 0.0);
-            xr[r] = rint(ldexp(v.x, e1));
-            xi[r] = rint(ldexp(v.y, e1));
-        }
+        for (int r = 0; r < 16; ++r) v[r] = col < np ? P[col * ld + r0 + r] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xr[r] = rint(ldexp(v[r].x, ex));
         write_residues(xr, mt, L + off, mstride);
-        write_residues(xi, mt, L + off + 512, mstride);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xr[r] = rint(ldexp(v[r].y, ex));
+        write_residues(xr, mt, L + off + 512, mstride);
     } else if (MODE == 0) {
-        // two passes over the 16 rows, residues of P then of d.P (w = 1 leaves P exact), so only
-        // one operand's values are live at a time; the second pass re-reads the rows from cache
-#pragma unroll 1
-        for (int ph = 0; ph < 2; ++ph) {
-            const int e = ph == 0 ? eL[col] : eRS[col];
+        // P is read once; the four operands (Re P, Im P, Re d.P, Im d.P) are formed and reduced one
+        // at a time, so only the 16 values of P and one operand are live
+        const int e1 = eL[col], e2 = eRS[col];
+        double2 v[16];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const double2 v = col < np ? P[col * ld + r0 + r] : make_double2(0.0, 0.0);
-                const double w = ph == 0 ? 1.0 : d[r0 + r];
-                xr[r] = rint(ldexp(v.x * w, e));
-                xi[r] = rint(ldexp(v.y * w, e));
-            }
-            int8_t *o = ph == 0 ? L : RS;
-            write_residues(xr, mt, o + off, mstride);
-            write_residues(xi, mt, o + off + 512, mstride);
-        }
+        for (int r = 0; r < 16; ++r) v[r] = col < np ? P[col * ld + r0 + r] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xr[r] = rint(ldexp(v[r].x, e1));
+        write_residues(xr, mt, L + off, mstride);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xr[r] = rint(ldexp(v[r].y, e1));
+        write_residues(xr, mt, L + off + 512, mstride);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xr[r] = rint(ldexp(v[r].x * d[r0 + r], e2));
+        write_residues(xr, mt, RS + off, mstride);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xr[r] = rint(ldexp(v[r].y * d[r0 + r], e2));
+        write_residues(xr, mt, RS + off + 512, mstride);
     } else {
-        const int e3 = eRH[col];
+        const int ex = eRH[col];
+        double2 v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const double2 v = col < np ? Q[col * ld + r0 + r] : make_double2(0.0, 0.0);
-            xr[r] = rint(ldexp(v.x, e3));
-            xi[r] = rint(ldexp(v.y, e3));
-        }
+        for (int r = 0; r < 16; ++r) v[r] = col < np ? Q[col * ld + r0 + r] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xr[r] = rint(ldexp(v[r].x, ex));
         write_residues(xr, mt, RH + off, mstride);
-        write_residues(xi, mt, RH + off + 512, mstride);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xr[r] = rint(ldexp(v[r].y, ex));
+        write_residues(xr, mt, RH + off + 512, mstride);
     }
 }
 
