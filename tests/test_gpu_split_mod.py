@@ -126,6 +126,35 @@ def test_mod_contract_random_operands(ctx, oracle_lib):
     assert _relfro(_upper(S.cpu().numpy()), So) < TOL_SPLIT
 
 
+@pytest.mark.parametrize("nm", [8, 14])
+def test_mod_single_entry_columns(ctx, oracle_lib, nm):
+    """Every column of P = [A; B] has one nonzero entry, so the column scaling turns it into an
+    integer within a factor 2 of 2^B: the largest magnitudes the residue step sees (B = 50 at 14
+    moduli), with mantissas up to 2 - 2^-40, signs and phases of all kinds, and magnitudes spread
+    over 2^-30..2^30 between columns.  A residue off by one modulus would come back from the
+    reconstruction as an error of order M/p relative to the scaled product, far above the bound."""
+    print(f"i8mod single-entry columns, {nm} moduli", flush=True)
+    cell = _mixed(n_g=200)
+    k, n = cell.k_rows(), 200
+    rng = np.random.default_rng(31 + nm)
+    rows = rng.integers(0, k, size=n)
+    mant = rng.uniform(1.0, 2.0, size=n)
+    mant[:16] = 2.0 - 2.0 ** -40
+    val = mant * 2.0 ** rng.integers(-30, 31, size=n) * np.exp(2j * np.pi * rng.uniform(size=n))
+    val[16:24] = mant[16:24] * np.array([1, -1, 1j, -1j, 1, -1, 1j, -1j]) * 2.0 ** 7   # real or imaginary only
+    A = np.zeros((k, n), np.complex128)
+    B = np.zeros((k, n), np.complex128)
+    cols = np.arange(n)
+    A[rows[0::2], cols[0::2]] = val[0::2]
+    B[rows[1::2], cols[1::2]] = val[1::2]
+    T = ctx.build_T(cell)
+    H, S = ctx.hs_contract(cell, _dev(A.T), _dev(B.T), T, prec="i8mod", slices=nm)
+    Ho, So = oracle_lib.hs_block(cell, oracle_lib.tmat_all(cell), A, B, A, B)
+    eh, es = _relfro(_upper(H.cpu().numpy()), Ho), _relfro(_upper(S.cpu().numpy()), So)
+    print(f"  B {_bits(nm)}: H {eh:.3e} S {es:.3e}", flush=True)
+    assert eh < 2.0 ** (8 - _bits(nm)) and es < 2.0 ** (8 - _bits(nm)), (eh, es)
+
+
 @pytest.mark.parametrize("lnonsph", [-1, 3])
 def test_mod_with_legendre_s(ctx, oracle_lib, lnonsph):
     """S by the addition theorem (FP64) and H by the modular contraction, dense and structured T."""
