@@ -477,11 +477,11 @@ ModProblemDev mod_problem(const ModArea &ma, double2 *H, double2 *S, long long l
 }
 
 flapw_status mod_slice_problem(flapw_handle h, const ProblemDev &pb, long long np, const ModArea &ma,
-                               const ModTable &mt, bool with_s, hipStream_t st)
+                               const ModTable &mt, bool with_s, const double *part, long long n_slots, hipStream_t st)
 {
     ProfScope prof(h, "slice", st);
     hipError_t e = launch_mod_slice(pb.P, pb.Q, pb.d, pb.ldp, pb.kp2, (int)np, (int)ma.npm, mt, ma.eL, ma.eRS, ma.eRH,
-                                    ma.L, ma.RS, ma.RH, with_s, st);
+                                    ma.L, ma.RS, ma.RH, with_s, part, n_slots, st);
     if (e != hipSuccess) return dev_fail(h, e, "residue slicing kernels");
     return FLAPW_OK;
 }
@@ -622,6 +622,8 @@ struct GenPlan {
     std::vector<GenBatch> batches;
     double2 *T = nullptr;
     unsigned char *tables = nullptr, *gaunt = nullptr, *desc = nullptr, *work = nullptr, *digits = nullptr;
+    double *part = nullptr;      // modular split: column-sum shares of the panel kernel (in work)
+    long long n_slots = 0;       // their (atom, row tile) slots
     unsigned char *legbuf = nullptr;                         // khat, ab, E of one k-point
     size_t leg_ab = 0, leg_E = 0;                            // byte offsets inside `leg`
 };
@@ -737,7 +739,10 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     if (const char *env = std::getenv("FLAPW_WORK_FRACTION")) frac = std::atof(env);
     long long np_max = 0;
     for (int i = 0; i < n_k; ++i) np_max = std::max(np_max, p.np[i]);
-    const size_t panel_one = (size_t)2 * L.kp2 * np_max * sizeof(double2);
+    // split: one k-point's P and Q; modular split also the column-sum shares after them
+    const size_t panel_pq = (size_t)2 * L.kp2 * np_max * sizeof(double2);
+    const size_t panel_one =
+        panel_pq + (p.mod ? (size_t)round_up(qpanel_colsum_doubles(p.ldt, p.n_atoms, np_max) * 8, 256) : 0);
     size_t budget = (size_t)(frac * (double)total_b);
     // never more than the device holds now: free memory plus this call's own work and digit
     // buffers, which are freed and allocated again when they must grow (10 % held back for the
@@ -775,6 +780,10 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
         if ((e = b.work->ensure(biggest)) != hipSuccess) return dev_fail(h, e, "allocating work buffer");
     }
     p.work = (unsigned char *)b.work->p;
+    if (p.mod) {
+        p.part = (double *)(p.work + panel_pq);
+        p.n_slots = (long long)qpanel_row_tiles(p.ldt) * p.n_atoms;
+    }
     if (p.leg) {
         const size_t lb = leg_bytes(L, np_max, p.n_types, &p.leg_ab, &p.leg_E);
         if ((e = b.leg->ensure(lb)) != hipSuccess) return dev_fail(h, e, "allocating Legendre scratch");
@@ -889,7 +898,8 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
                 e = launch_qpanel(p.T, p.ldt, p.ldt * p.ldt, (const int *)(p.tables + p.oty),
                                   (const int *)(p.tables + p.onl), (const long long *)(p.tables + p.orow), p.n_atoms, P,
                                   Q, L.kp2, (int)p.np[i], L.kp2, true,
-                                  *std::min_element(L.atom_nl2.begin(), L.atom_nl2.end()), s);
+                                  *std::min_element(L.atom_nl2.begin(), L.atom_nl2.end()),
+                                  (const double *)(p.tables + p.od), p.part, s);
             }
             if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
             if (p.split) {
@@ -897,7 +907,9 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
                                     (int)L.kp2};
                 if (p.mod) {
                     const ModArea ma = mod_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl);
-                    if ((st = mod_slice_problem(h, pd, p.np[i], ma, p.mt, !p.leg, s)) != FLAPW_OK) return st;
+                    if ((st = mod_slice_problem(h, pd, p.np[i], ma, p.mt, !p.leg, p.part, p.n_slots, s)) !=
+                        FLAPW_OK)
+                        return st;
                 } else {
                     const DigitArea da = digit_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl, p.bf16 ? 2 : 1);
                     if ((st = slice_problem(h, pd, p.np[i], p.sl, da, p.bf16, s)) != FLAPW_OK) return st;
@@ -1310,7 +1322,8 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
     {
         ProfScope prof(h, "qpanel", s);
         e = launch_qpanel((const double2 *)T, ldt, ldt * ldt, (const int *)(base + oty), (const int *)(base + onl),
-                          (const long long *)(base + orow), at->n_atoms, P, Q, L.kp2, (int)np, L.kp2, false, 0, s);
+                          (const long long *)(base + orow), at->n_atoms, P, Q, L.kp2, (int)np, L.kp2, false, 0,
+                          nullptr, nullptr, s);
     }
     if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
     ProblemDev pd{P, Q, (const double *)(base + od), (double2 *)H, (double2 *)S, L.kp2, ldh, n_g, (int)L.kp2};
@@ -1323,7 +1336,7 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
         if (e != hipSuccess) return dev_fail(h, e, "allocating residue buffer");
         const ModArea ma = mod_area(h->digits.p, L.kp2, np, sl);
         const ModTable mt = make_mod_table(sl);
-        if ((st = mod_slice_problem(h, pd, np, ma, mt, true, s)) != FLAPW_OK) return st;
+        if ((st = mod_slice_problem(h, pd, np, ma, mt, true, nullptr, 0, s)) != FLAPW_OK) return st;
         std::vector<TileDev> blocks, tiles;
         build_mod_tiles({(int)(ma.npm / kModTile)}, 0, 2, blocks, band);
         build_tiles({(int)(ma.npm / kModTile)}, 0, 2, tiles, band);

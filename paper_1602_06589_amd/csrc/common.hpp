@@ -91,9 +91,19 @@ hipError_t launch_tmat(int n_types, const int *lmax_dev, int lstride, int lpot, 
 
 // Q_a = T_type(a) P_a for every atom; rows from the end of the last atom block up to kp2 are set
 // to zero.  real_t: T is known to be real (built by the library from real integrals): half the MFMAs
+// Q_a = T_a P_a for every atom.  With part (real T only; d the row weights), the real-T kernel also
+// writes per (atom, row tile) shares of the column sums sum |P|^2, sum |P|^2 d^2 and sum |Q|^2:
+// 3 x qpanel_row_tiles(ldt) x n_atoms x np doubles (qpanel_colsum_doubles), summed by
+// launch_mod_slice.
+constexpr int kQRowsPerTile = 256;
+inline int qpanel_row_tiles(long long ldt) { return (int)((ldt + kQRowsPerTile - 1) / kQRowsPerTile); }
+inline long long qpanel_colsum_doubles(long long ldt, int n_atoms, long long np)
+{
+    return 3LL * qpanel_row_tiles(ldt) * n_atoms * np;
+}
 hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, const int *atom_type, const int *atom_nl2,
                          const long long *atom_row, int n_atoms, const double2 *P, double2 *Q, long long ldp, int np,
-                         long long kp2, bool real_t, int min_nl2, hipStream_t s);
+                         long long kp2, bool real_t, int min_nl2, const double *d, double *part, hipStream_t s);
 
 // with_s = false: H alone (S tiles of the problems are not touched)
 hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_tiles, bool with_s, hipStream_t s);
@@ -171,9 +181,11 @@ ModTable make_mod_table(int nm);
 hipError_t init_mod_kernels();    // dynamic-LDS attribute of the contraction (before launch or capture)
 long long mod_digit_bytes(long long kp2, long long npm, int nm);
 long long mod_scratch_bytes(long long npm, int nm);
+// with_s = false: no S operand.  part: the column-sum shares of the real-T panel kernel over
+// n_slots (atom, row tile) slots, or nullptr to read the column norms from P and Q.
 hipError_t launch_mod_slice(const double2 *P, const double2 *Q, const double *d, long long ld, int kp2, int np,
                             int npm, const ModTable &mt, int *eL, int *eRS, int *eRH, int8_t *L, int8_t *RS,
-                            int8_t *RH, bool with_s, hipStream_t s);   // with_s = false: no S operand
+                            int8_t *RH, bool with_s, const double *part, long long n_slots, hipStream_t s);
 hipError_t launch_mod_contract(const ModProblemDev *probs, const TileDev *tiles, int n_tiles, const ModTable &mt,
                                hipStream_t s);
 hipError_t launch_mod_crt(const ModProblemDev *probs, const TileDev *tiles, int n_tiles, const ModTable &mt,

@@ -324,6 +324,7 @@ __global__ __launch_bounds__(kThreads, 1) void qpanel_kernel(const double2 *__re
 
 constexpr int kQRows = 256;                 // rows of Q_a per block of the real-T kernel
 constexpr int kQThreads = 512;
+static_assert(kQRows == kQRowsPerTile, "row tile of the real-T panel kernel");
 
 struct QRealSmem {
     double x[2][kQRows][kSlot];             // [buffer][row of Q_a = column of T][k], Re T
@@ -341,11 +342,17 @@ struct QRealSmem {
 // tiles of one atom follow each other on one XCD and find T of its type in that XCD's L2.
 // FULL: every atom of the launch has 2NL > 240 and one row tile, so every row block of every wave
 // holds rows and the per-block tests (which cost a few per cent) compile away.
-template <bool FULL>
+// NORMS: the block also writes its share of three column sums, sum |P|^2, sum |P|^2 d^2 (d the row
+// weights) over the atom's rows and sum |Q|^2 over the tile's rows, to part[(k n_slots + slot) np
+// + column] for k = 0, 1, 2 and slot = atom * row_tiles + row tile (the P sums only from row tile
+// 0, zeros from the others), each reduced in a fixed order, so that the sums over slots are
+// reproducible.  Those squared column norms set the integer scaling of the modular contraction.
+template <bool FULL, bool NORMS>
 __global__ __launch_bounds__(kQThreads, 1) void qpanel_real_kernel(
     const double2 *__restrict__ T, long long ldt, long long tstride, const int *__restrict__ atom_type,
     const int *__restrict__ atom_nl2, const long long *__restrict__ atom_row, const double2 *__restrict__ P,
-    double2 *__restrict__ Q, long long ldp, int n_atoms, long long kp2, int n_ct, int row_tiles, long long per_xcd)
+    double2 *__restrict__ Q, long long ldp, int n_atoms, long long kp2, int n_ct, int row_tiles, long long per_xcd,
+    const double *__restrict__ dw, double *__restrict__ part, long long np)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     QRealSmem &sm = *reinterpret_cast<QRealSmem *>(smem_raw);
@@ -367,7 +374,12 @@ __global__ __launch_bounds__(kQThreads, 1) void qpanel_real_kernel(
     }
     const int m2 = atom_nl2[a];                         // 2 NL of this atom
     const int r0 = rt * kQRows;
-    if (r0 >= m2) return;
+    const long long n_slots = (long long)n_atoms * row_tiles, slot = (long long)a * row_tiles + rt;
+    if (r0 >= m2) {                                     // no rows here: zero shares
+        if (NORMS && threadIdx.x < 3 * kTile)
+            part[((threadIdx.x >> 6) * n_slots + slot) * np + c0 + (threadIdx.x & 63)] = 0.0;
+        return;
+    }
     const long long prow = atom_row[a];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -393,6 +405,8 @@ __global__ __launch_bounds__(kQThreads, 1) void qpanel_real_kernel(
 
     double xv[8];
     double2 yv[2];
+    double sp[2] = {0.0, 0.0}, sd[2] = {0.0, 0.0};     // NORMS: this lane's rows of columns lg + 32 j
+    double wv = 0.0;                                    // NORMS: weight of the loaded row
     auto load = [&](int kt) {
         const int kb = kt * kKTile;
         const bool k_ok = kb + lk < m2;
@@ -406,8 +420,18 @@ __global__ __launch_bounds__(kQThreads, 1) void qpanel_real_kernel(
             yv[j] = make_double2(0.0, 0.0);
             if (k_ok) yv[j] = gY[32LL * j * ldp + kb];
         }
+        if (NORMS) wv = k_ok ? dw[prow + kb + lk] : 0.0;
     };
+    // the sums use the loaded values here, after the stage's MFMAs have covered the loads
     auto store = [&](int b) {
+        if (NORMS) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const double a2 = yv[j].x * yv[j].x + yv[j].y * yv[j].y;
+                sp[j] += a2;
+                sd[j] += a2 * wv * wv;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < 8; ++j) sm.x[b][lg + 32 * j][lk] = xv[j];
 #pragma unroll
@@ -448,6 +472,48 @@ __global__ __launch_bounds__(kQThreads, 1) void qpanel_real_kernel(
         }
         if (kt + 1 < nkt) store(b ^ 1);
         __syncthreads();
+    }
+    if (NORMS) {
+        // P sums: the 16 lanes of a loader group hold the rows of the same two columns
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                sp[j] += __shfl_xor(sp[j], o);
+                sd[j] += __shfl_xor(sd[j], o);
+            }
+        if (lk == 0) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const long long col = c0 + lg + 32 * j;
+                part[slot * np + col] = rt == 0 ? sp[j] : 0.0;
+                part[(n_slots + slot) * np + col] = rt == 0 ? sd[j] : 0.0;
+            }
+        }
+        // Q sums: rows of the lane's accumulators (zero in row blocks past 2NL), then the four lane
+        // groups of a column, then the four waves with the same columns, through LDS (the stage
+        // buffers are free after the last barrier)
+        double sq[2];
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) {
+            sq[ni] = 0.0;
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    sq[ni] += acc[0][mi][ni][r] * acc[0][mi][ni][r] + acc[1][mi][ni][r] * acc[1][mi][ni][r];
+            sq[ni] += __shfl_xor(sq[ni], 16);
+            sq[ni] += __shfl_xor(sq[ni], 32);
+        }
+        double *red = &sm.x[0][0][0];                   // [wr][64 columns]
+        if (lane < 16) {
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni) red[wr * kTile + wn + ni * 16 + lane] = sq[ni];
+        }
+        __syncthreads();
+        if (tid < kTile)
+            part[(2 * n_slots + slot) * np + c0 + tid] =
+                ((red[tid] + red[kTile + tid]) + red[2 * kTile + tid]) + red[3 * kTile + tid];
     }
     if (!active) return;
     // T is symmetric, so the product of its columns with P is T P.
@@ -494,12 +560,10 @@ hipError_t init_fp64_kernels()
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)qpanel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sizeof(QSmem));
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)qpanel_real_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sizeof(QRealSmem));
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)qpanel_real_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sizeof(QRealSmem));
+    const void *qreal[4] = {(const void *)qpanel_real_kernel<true, false>, (const void *)qpanel_real_kernel<false, false>,
+                            (const void *)qpanel_real_kernel<true, true>, (const void *)qpanel_real_kernel<false, true>};
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+        e = hipFuncSetAttribute(qreal[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(QRealSmem));
     done = e;
     return e;
 }
@@ -517,26 +581,34 @@ hipError_t launch_hs_fp64(const ProblemDev *probs, const TileDev *tiles, int n_t
 
 hipError_t launch_qpanel(const double2 *T, long long ldt, long long tstride, const int *atom_type, const int *atom_nl2,
                          const long long *atom_row, int n_atoms, const double2 *P, double2 *Q, long long ldp, int np,
-                         long long kp2, bool real_t, int min_nl2, hipStream_t s)
+                         long long kp2, bool real_t, int min_nl2, const double *d, double *part, hipStream_t s)
 {
     hipError_t e = init_fp64_kernels();
     if (e != hipSuccess) return e;
     const int n_ct = np / kTile;
     if (real_t) {
-        const int row_tiles = (int)((ldt + kQRows - 1) / kQRows);
+        const int row_tiles = qpanel_row_tiles(ldt);
         const long long units = (long long)(n_atoms + 1) * n_ct * row_tiles;
         const long long per_xcd = (units + 7) / 8;
         if (8 * per_xcd > 0x7fffffffLL) return hipErrorInvalidValue;
-        if (row_tiles == 1 && min_nl2 > kQRows - 16)
-            hipLaunchKernelGGL(qpanel_real_kernel<true>, dim3((unsigned)(8 * per_xcd)), dim3(kQThreads), sizeof(QRealSmem),
-                               s, T, ldt, tstride, atom_type, atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2, n_ct, row_tiles,
-                               per_xcd);
-        else
-            hipLaunchKernelGGL(qpanel_real_kernel<false>, dim3((unsigned)(8 * per_xcd)), dim3(kQThreads), sizeof(QRealSmem),
-                               s, T, ldt, tstride, atom_type, atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2, n_ct, row_tiles,
-                               per_xcd);
+        if (part && !d) return hipErrorInvalidValue;
+        const bool full = row_tiles == 1 && min_nl2 > kQRows - 16;
+        const dim3 grid((unsigned)(8 * per_xcd));
+#define QREAL(F, N)                                                                                                    \
+    hipLaunchKernelGGL((qpanel_real_kernel<F, N>), grid, dim3(kQThreads), sizeof(QRealSmem), s, T, ldt, tstride,         \
+                       atom_type, atom_nl2, atom_row, P, Q, ldp, n_atoms, kp2, n_ct, row_tiles, per_xcd, d, part,      \
+                       (long long)np)
+        if (part) {
+            if (full) QREAL(true, true);
+            else QREAL(false, true);
+        } else {
+            if (full) QREAL(true, false);
+            else QREAL(false, false);
+        }
+#undef QREAL
         return hipGetLastError();
     }
+    if (part) return hipErrorInvalidValue;             // column sums only from the real-T kernel
     // row tiles: enough for the largest atom block (2 NL <= ldt)
     const int row_tiles = (int)((ldt + kTile - 1) / kTile);
     // units (atom, column tile), atom n_atoms zeroing the padding rows; 8 units per group of

@@ -27,6 +27,7 @@
 //
 // Kernels:
 //   mod_colnorm_kernel  per column: e_c of P, of d.P (right operand of S) and of Q (right of H)
+//   mod_colsum_kernel   the same e_c from column-sum shares written by the real-T panel kernel
 //   mod_slice_kernel    residues of all moduli, stored as [modulus][32-column block][16-row chunk]
 //                       [re, im][32 columns][16 bytes] (one 1 KB MFMA fragment per chunk)
 //   hs_mod_i8_kernel    one block per (256 x 128 output block, modulus): eight waves of 64 x 64,
@@ -117,6 +118,28 @@ __global__ __launch_bounds__(256) void mod_colnorm_kernel(const double2 *__restr
         eRS[c] = mod_exponent(red[1][0], bits);
         eRH[c] = mod_exponent(red[2][0], bits);
     }
+}
+
+// The same exponents from the column-sum shares that the real-T panel kernel wrote while forming
+// Q: part[(k n_slots + slot) np + c], k = 0, 1, 2 for sum |P|^2, sum |P|^2 d^2, sum |Q|^2, summed
+// over the slots in order (one thread per column, reads coalesced across columns).
+__global__ __launch_bounds__(256) void mod_colsum_kernel(const double *__restrict__ part, long long n_slots,
+                                                         long long np, int npm, int bits, int *__restrict__ eL,
+                                                         int *__restrict__ eRS, int *__restrict__ eRH)
+{
+    const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (c >= npm) return;
+    double sp = 0.0, sd = 0.0, sq = 0.0;
+    if (c < np) {
+        for (long long t = 0; t < n_slots; ++t) {
+            sp += part[t * np + c];
+            sd += part[(n_slots + t) * np + c];
+            sq += part[(2 * n_slots + t) * np + c];
+        }
+    }
+    eL[c] = mod_exponent(sp, bits);
+    eRS[c] = mod_exponent(sd, bits);
+    eRH[c] = mod_exponent(sq, bits);
 }
 
 // residues of 16 integer-valued doubles for every modulus, 16 bytes per modulus at out + m * mstride
@@ -493,9 +516,13 @@ long long mod_scratch_bytes(long long npm, int nm)
 
 hipError_t launch_mod_slice(const double2 *P, const double2 *Q, const double *d, long long ld, int kp2, int np,
                             int npm, const ModTable &mt, int *eL, int *eRS, int *eRH, int8_t *L, int8_t *RS,
-                            int8_t *RH, bool with_s, hipStream_t s)
+                            int8_t *RH, bool with_s, const double *part, long long n_slots, hipStream_t s)
 {
-    hipLaunchKernelGGL(mod_colnorm_kernel, dim3(npm), dim3(256), 0, s, P, Q, d, ld, kp2, np, mt.bits, eL, eRS, eRH);
+    if (part)
+        hipLaunchKernelGGL(mod_colsum_kernel, dim3((npm + 255) / 256), dim3(256), 0, s, part, n_slots, (long long)np, npm,
+                           mt.bits, eL, eRS, eRH);
+    else
+        hipLaunchKernelGGL(mod_colnorm_kernel, dim3(npm), dim3(256), 0, s, P, Q, d, ld, kp2, np, mt.bits, eL, eRS, eRH);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid(npm / 32, kp2 / 128);

@@ -79,6 +79,15 @@ def test_caps_single_atom(handles, oracle_lib, prec, method):
 
 @pytest.mark.parametrize("method", ["gemm", "legendre"])
 @pytest.mark.parametrize("prec", ["fp64", "i8", "bf16", "i8mod"])
+def test_mixed_row_tiles(handles, oracle_lib, prec, method):
+    """l_max 12 and 5 (2 NL = 338 and 72): the Q panels take two 256-row tiles, and the second
+    tile of the l_max 5 atoms holds no rows (zero column-sum shares for the modular scaling)."""
+    cell = _cell(170, types=(0, 1, 1), lmax=(12, 5), lpot=6, seed=23, a=8.0)
+    _check_full(handles, oracle_lib, cell, prec, method)
+
+
+@pytest.mark.parametrize("method", ["gemm", "legendre"])
+@pytest.mark.parametrize("prec", ["fp64", "i8", "bf16", "i8mod"])
 def test_smallest_lmax(handles, oracle_lib, prec, method):
     """Atoms with l_max 0 and 1 (2NL = 2 and 8 rows): most Q-panel waves hold no rows."""
     cell = _cell(150, types=(0, 1, 1, 0), lmax=(0, 1), lpot=2, seed=17)
