@@ -1,28 +1,34 @@
 #!/usr/bin/env python3
 """Benchmark: H and S generation (coefficients -> T -> per-atom panels -> S/H contractions) on
-one MI355X, for the seeded synthetic workloads of synthcells.
+one MI355X, for the seeded synthetic workloads of synthcells (default: the 512-atom workload, 4
+k-points).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--precs i8mod,i8,fp64,i8mod+leg,fp64+leg]
-                    [--slices s | --no-tune]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--precs i8mod,fp64]
+                    [--slices s | --no-tune] [--eager] [--ceiling] [--budget-s 420]
 
-A path is a precision (i8mod, i8, bf16 or fp64 for the S/H contraction) with an optional "+leg": S then
-comes from the addition theorem (section 3.1) and the contraction computes H alone.  The first
-path is the headline.
+A path is a precision (i8mod, i8, bf16 or fp64 for the S/H contraction) with an optional "+leg": S
+then comes from the addition theorem (section 3.1) and the contraction computes H alone.  The
+first path is the headline; the default pair is the modular int8 split and the FP64 comparator.
 Before its timing, each split path runs the library's autotuner on k-point 0 (flapw_tune: the
-smallest digit or modulus count whose H and S errors on a sampled block are at most 1e-10 / 4,
-then the fastest tile band); --slices fixes the count instead and --no-tune takes the defaults.
-A step is one flapw_hs_generate call over every k-point of the workload (the whole path).
-Inputs (G lists) are resident in HBM before timing starts; K timed steps are bracketed by
-torch.cuda.synchronize().  Prints one JSON line:
-  value      algorithmic TFLOP/s of the headline path (the first of --precs), F_alg per k-point
-             = 16 K N(N+1) + 32 N sum_a NL_a^2 (S and H upper triangles + panels T_a P_a)
-  roofline   the dominant kernel (the S/H contraction), its average launch time from HIP events
-             recorded by the library on the launch stream
-  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload; the sampled
-             entries also give the relative Frobenius error of every measured path
-  radial_setup  the step upstream of the coefficients and T: radial functions and the integral
-             tables of the workload's atom types from synthetic radial meshes (--radial-nr points),
-             GPU time per call and, beside it, the oracle's time and deviation
+smallest modulus or digit count whose H and S errors, extrapolated from a sampled block to the
+whole matrix, are at most 1e-10 / 2, then the fastest tile band); --slices fixes the count
+instead and --no-tune takes the defaults.
+A step is one generation over every k-point of the workload (the whole path), replayed from a
+HIP graph (flapw_plan_launch; --eager: flapw_hs_generate calls).  The headline takes W untimed
+and K timed steps; every other path at most 1 and 3 (a wall-clock guard trims them further and
+says so).  Each timed step lies between HIP events on the launch stream; the timed region is
+bracketed by torch.cuda.synchronize().  G lists are resident in HBM before timing starts.
+Prints one JSON line:
+  value         algorithmic TFLOP/s of the headline from the median step time, F_alg per
+                k-point = 16 K N(N+1) + 32 N sum_a NL_a^2 (S and H upper triangles + panels)
+  ms_per_step   that median (mean, minimum and the host-clock mean beside it in "paths")
+  roofline      the dominant kernel (the S/H contraction): its average launch time from the HIP
+                events the library records on the launch stream during eager profiled steps
+  rel_err       per matrix, the relative Frobenius error of the whole k-point-0 matrix estimated
+                without bias from a random principal submatrix against the oracle
+  cpu_baseline  the oracle timed on that sample, with the time of a whole k-point extrapolated
+  radial_setup  radial functions and integral tables of the workload's atom types from synthetic
+                meshes (--radial-nr points): GPU time per call, the oracle's time and deviation
 """
 from __future__ import annotations
 
@@ -74,38 +80,92 @@ def read_traffic(prec: str, workload: str):
     return None
 
 
-def cpu_baseline_leg(cell, outs, nsamp: int, lnonsph: int = -1):
-    """The oracle on a bounded sample (k-point 0: an nsamp x nsamp block of basis functions,
-    H and S), timed on the host cores.  Also returns the relative Frobenius error of each GPU
-    path on those entries (upper triangle)."""
+def oracle_threads() -> int:
+    """Threads the oracle's OpenMP loops use (libgomp's own count), else the visible cores."""
+    import ctypes
+    try:
+        return int(ctypes.CDLL("libgomp.so.1").omp_get_max_threads())
+    except OSError:
+        return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def sample_indices(n: int, nsamp: int, seed: int = 4242) -> np.ndarray:
+    """A uniform random subset of the basis functions of one k-point (sorted)."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, min(nsamp, n), replace=False))
+
+
+def gather_block(M, idx: np.ndarray) -> np.ndarray:
+    """Entries (idx[a], idx[b]), a <= b, of an upper-triangle result tensor (M[c][r] = entry (r, c)),
+    gathered on the device and copied to the host; the strictly lower part of the block is zero."""
+    import torch
+    ii = torch.as_tensor(idx, device=M.device)
+    sub = M.index_select(0, ii).index_select(1, ii).transpose(0, 1).cpu().numpy()
+    return np.triu(sub)
+
+
+def error_estimates(got: np.ndarray, ref: np.ndarray, n_full: int) -> dict:
+    """Errors of a result on the principal submatrix of a uniform random index sample.
+    sample_relF: relative Frobenius error of the sample's upper triangle as it stands.
+    full_relF_est: the same for the whole Hermitian matrix, from the sample reweighted so that the
+    estimate of every squared norm is unbiased: the n sampled diagonal entries stand for the N
+    diagonal entries (factor N/n), the n(n-1)/2 sampled pairs t' < t for the N(N-1)/2 pairs
+    (factor N(N-1)/(n(n-1))), and the strict upper triangle counts twice (Hermitian).
+    max_err_over_max: max |dX| over max |X| on the sample."""
+    n = got.shape[0]
+    iu = np.triu_indices(n, 1)
+    d = np.arange(n)
+    e2 = np.abs(got - ref) ** 2
+    r2 = np.abs(ref) ** 2
+    wd = n_full / n
+    wo = n_full * (n_full - 1.0) / (n * (n - 1.0)) if n > 1 else 0.0
+    num = wd * e2[d, d].sum() + 2.0 * wo * e2[iu].sum()
+    den = wd * r2[d, d].sum() + 2.0 * wo * r2[iu].sum()
+    up = np.triu(np.ones((n, n), bool))
+    return {"sample_relF": float(np.sqrt(e2[up].sum() / r2[up].sum())),
+            "full_relF_est": float(np.sqrt(num / den)),
+            "max_err_over_max": float(np.sqrt(e2[up].max() / r2[up].max()))}
+
+
+def cpu_baseline_leg(cell, idx: np.ndarray, lnonsph: int = -1):
+    """The oracle on a bounded sample of k-point 0: H and S on the principal submatrix of the
+    random basis-function subset idx (coefficients of those columns, T, per-atom panels, entries),
+    timed on the host cores, plus a one-row block that isolates the per-column panel cost.  The
+    time of a whole k-point is extrapolated from those parts (coefficients and panels per column,
+    entries per upper-triangle entry) and labelled as such.  Returns (baseline, (H, S) of the
+    sample)."""
     import oracle
     oracle._load()
     ik = 0
-    n = cell.n_g(ik)
-    rng = np.random.default_rng(4242)
-    idx = np.sort(rng.choice(n, min(nsamp, n), replace=False))
+    n_full = cell.n_g(ik)
+    ns = len(idx)
     t0 = time.perf_counter()
     T = oracle.tmat_all(cell, lnonsph=lnonsph)
-    Ho, So = oracle.hs_sampled(cell, ik, idx, idx, T)
-    dt = time.perf_counter() - t0
+    t_T = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    A, B = oracle.coeffs(cell, ik, idx)
+    t_coef = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Ho, So = oracle.hs_block(cell, T, A, B, A, B)
+    t_blk = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.hs_block(cell, T, A[:, :1], B[:, :1], A, B)          # one bra row: the panels of ns columns
+    t_panel = time.perf_counter() - t0
+    t_entry = max(t_blk - t_panel, 1e-9) / float(ns * ns)
+    dt = t_T + t_coef + t_blk
     k = cell.k_rows()
     nl = cell.nl_atom().astype(float)
-    flops = 2 * len(idx) * len(idx) * 16.0 * k + 2 * len(idx) * 32.0 * float((nl * nl).sum())
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    up = idx[:, None] <= idx[None, :]
-    errs = {}
-    for prec, (H, S) in outs.items():
-        Hn, Sn = H.cpu().numpy(), S.cpu().numpy()
-        e = {}
-        for name, M, R in (("H", Hn, Ho), ("S", Sn, So)):
-            got = M[np.ix_(idx, idx)].T
-            e[name] = float(np.linalg.norm((got - R)[up]) / np.linalg.norm(R[up]))
-        errs[prec] = e
-    base = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"k-point 0 of {cell.name}: H and S on a {len(idx)}x{len(idx)} block of basis functions "
-                      f"(coefficients of those columns, T, per-atom panels), {dt:.1f} s",
-            "seconds": dt}
-    return base, errs
+    flops = 32.0 * k * ns * ns + ns * 32.0 * float((nl * nl).sum())   # S and H entries + panels
+    t_kpt = t_T + (t_coef + t_panel) * n_full / ns + t_entry * n_full * (n_full + 1) / 2.0
+    base = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": oracle_threads(), "kind": "oracle",
+            "sample": f"k-point 0 of {cell.name}: H and S on the {ns}x{ns} principal submatrix of a random subset "
+                      f"of its {n_full} basis functions (T, coefficients of those columns, per-atom panels, "
+                      f"{ns * ns} entries), {dt:.1f} s",
+            "seconds": dt,
+            "seconds_per_kpoint_extrapolated": t_kpt,
+            "extrapolation": f"T {t_T:.2f} s + (coefficients {t_coef:.2f} s + panels {t_panel:.2f} s) x N/{ns} + "
+                             f"{t_entry * 1e6:.1f} us per entry x N(N+1)/2, N = {n_full}"}
+    return base, (Ho, So)
 
 
 def radial_leg(cell, n_r: int, steps: int, with_oracle: bool):
@@ -151,29 +211,42 @@ def mfma_ceiling():
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
-def main():
+def step_plan(is_head: bool, steps: int, warmup: int):
+    """(warm-up replays, timed replays, eager profiled steps) of a path: the headline takes the
+    requested counts; every other path at most 1 warm-up and 3 timed replays, and one eager step
+    for its kernel breakdown (the headline: up to 3, after one eager warm-up)."""
+    if is_head:
+        return warmup, steps, min(3, max(1, steps))
+    return min(warmup, 1), min(steps, 3), 1
+
+
+def make_parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed graph replays of the headline path")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed graph replays before them")
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--precs", default="i8mod,i8,fp64,i8mod+leg,fp64+leg",
-                    help="paths to measure; the first is the headline (value, roofline)")
+    ap.add_argument("--precs", default="i8mod,fp64",
+                    help="paths to measure; the first is the headline (value, roofline); others: i8, bf16 and "
+                         "'+leg' variants (S through the addition theorem)")
     ap.add_argument("--slices", type=int, default=0)
     ap.add_argument("--s-method", default="gemm", choices=["gemm", "legendre"],
                     help="S method of paths without a '+leg' suffix")
     ap.add_argument("--nk", type=int, default=0, help="use only the first nk k-points (0 = all)")
     ap.add_argument("--lnonsph", type=int, default=-1,
                     help="structured T: non-spherical terms only for l', l <= lnonsph (-1: dense T, the default)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time the headline by eager flapw_hs_generate calls instead of graph replays")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-clock guard: paths after the headline drop timed steps (and the radial leg is "
+                         "skipped) when the run would otherwise pass this many seconds; the line records it")
     ap.add_argument("--mfma-ceiling", action="store_true",
                     help="only run the matrix-core rate microbenchmark (constant and random operands) and exit")
-    ap.add_argument("--no-ceiling", action="store_true", help="skip the matrix-core rate microbenchmark")
-    ap.add_argument("--graph", action="store_true",
-                    help="also time replays of the generation captured in a HIP graph (flapw_plan_*)")
+    ap.add_argument("--ceiling", action="store_true",
+                    help="also run the matrix-core rate microbenchmark and report the headline against it")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner and use the library's default digit or modulus count and tile "
-                         "band (by default each split path is tuned on k-point 0 before timing: the smallest "
-                         "count whose sampled error is at most 1e-10 / 4, then the fastest band)")
+                         "band (by default each split path is tuned on k-point 0 before timing)")
     ap.add_argument("--cpu-sample", type=int, default=384)
     ap.add_argument("--radial-nr", type=int, default=1001,
                     help="mesh points of the radial-setup leg (radial functions and integrals of the "
@@ -182,7 +255,12 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (calibrates the "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters against known bytes) and exit")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = make_parser().parse_args()
+    t_start = time.perf_counter()
 
     if args.mfma_ceiling:
         print(json.dumps(mfma_ceiling()))
@@ -220,6 +298,7 @@ def main():
     # algorithmic flops of the contraction kernel: S and H triangles, or H alone when S comes from
     # the addition theorem
     per_mat = [8.0 * kr * cell.n_g(i) * (cell.n_g(i) + 1.0) for i in range(nk)]
+    idx = sample_indices(cell.n_g(0), args.cpu_sample)
 
     def split_path(path):
         prec, _, suffix = path.partition("+")
@@ -230,10 +309,14 @@ def main():
           f"N_G {min(cell.n_g(i) for i in range(nk))}..{max(cell.n_g(i) for i in range(nk))}, "
           f"F_alg {sum(f_alg):.3e}", flush=True)
 
-    results, outs = {}, {}
-    for path in precs:
+    results, samples = {}, {}
+    for pi, path in enumerate(precs):
+        is_head = pi == 0
         prec, s_method = split_path(path)
         f_contract = [(2.0 if s_method == "gemm" else 1.0) * x for x in per_mat]
+        n_warm, n_time, n_eager = step_plan(is_head, args.steps, args.warmup)
+        use_graph = not (is_head and args.eager)
+        notes = []
         with Flapw() as fl:                   # one handle per path: its work buffers are freed after
             fl.set_s_method(s_method)
             fl.set_lnonsph(args.lnonsph)
@@ -246,59 +329,103 @@ def main():
                     tuned = {"error": str(err)}
                 tuned["seconds"] = time.perf_counter() - t0
                 print(f"# {path}: tuned {json.dumps(tuned)}", flush=True)
+                fl.release_workspace()            # the plan below owns its own buffers
             out = [(torch.zeros((cell.n_g(i), cell.n_g(i)), dtype=torch.complex128, device="cuda"),
                     torch.zeros((cell.n_g(i), cell.n_g(i)), dtype=torch.complex128, device="cuda")) for i in range(nk)]
-            for _ in range(args.warmup):
+
+            def timed(run, n_w, n_t, label, guard=False):
+                """n_w untimed runs, then n_t runs each between HIP events on the stream; the whole
+                timed region is bracketed by synchronisations.  With guard, n_t shrinks so that the
+                run keeps to the wall-clock budget (judged from the first untimed run).  Returns the
+                per-run ms and the wall time."""
+                t_one = None
+                for w in range(n_w):
+                    t0 = time.perf_counter()
+                    run()
+                    torch.cuda.synchronize()
+                    if w == 0:
+                        t_one = time.perf_counter() - t0
+                torch.cuda.synchronize()
+                if guard and t_one is not None:
+                    left = args.budget_s - (time.perf_counter() - t_start) - 2.0 * t_one   # the eager steps
+                    fit = int(left / t_one)
+                    if fit < n_t:
+                        n_t = max(1, fit)
+                        notes.append(f"wall-clock guard: {n_t} timed run(s) of {label} "
+                                     f"({max(left, 0):.0f} s left of {args.budget_s:.0f})")
+                evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                       for _ in range(n_t)]
+                t0 = time.perf_counter()
+                for a, b in evs:
+                    a.record(stream)
+                    run()
+                    b.record(stream)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                per = [a.elapsed_time(b) for a, b in evs]
+                print(f"# {path}: {label} {n_t} runs, median {np.median(per):.2f} ms, wall {wall:.1f} s", flush=True)
+                return per, wall
+
+            if not is_head:
+                n_warm = max(1, n_warm)          # the guard judges a path by its first untimed run
+            rec = {"s_method": s_method, "tuned": tuned}
+            if use_graph:
+                with fl.plan(cell, cell.kpts, gdev, prec=prec, slices=args.slices, out=out) as plan:
+                    per, wall = timed(lambda: plan.launch(stream), n_warm, n_time, "graph replay", not is_head)
+                rec["timing"] = "median of HIP-graph replays (flapw_plan_launch)"
+            else:
+                per, wall = timed(lambda: fl.hs_generate(cell, cell.kpts, gdev, prec=prec, slices=args.slices,
+                                                         out=out), n_warm, n_time, "eager", not is_head)
+                rec["timing"] = "median of eager flapw_hs_generate calls"
+            med = float(np.median(per))
+            rec.update({"steps": n_time, "warmup": n_warm, "ms_per_step": med,
+                        "ms_per_step_mean": float(np.mean(per)), "ms_per_step_min": float(np.min(per)),
+                        "wall_ms_per_step": wall * 1e3 / n_time, "ms_per_kpoint": med / nk,
+                        "tflops": sum(f_alg) / (med * 1e-3) / 1e12})
+            # eager steps with the library's per-kernel HIP events: the stage breakdown and the
+            # contraction kernel's average launch time
+            if is_head:          # eager warm-up (the kernels' own event times need none)
                 fl.hs_generate(cell, cell.kpts, gdev, prec=prec, slices=args.slices, out=out)
             torch.cuda.synchronize()
             fl.profile(True)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            e0.record(stream)
-            for _ in range(args.steps):
-                fl.hs_generate(cell, cell.kpts, gdev, prec=prec, slices=args.slices, out=out)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-            ms = e0.elapsed_time(e1) / args.steps
+            per_e, _ = timed(lambda: fl.hs_generate(cell, cell.kpts, gdev, prec=prec, slices=args.slices, out=out),
+                             0, n_eager, "eager (profiled)")
             kern = {fam: fl.kernel_time(fam)
                     for fam in ("coeffs", "tmat", "qpanel", "hs_fp64", "slice", "hs_split", "hs_mod", "mod_crt",
                                 "leg_prep", "s_legendre")}
             fl.profile(False)
             n_l, k_ms = kern[KERNEL[prec]]
-            achieved = sum(f_contract) * args.steps / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
-            results[path] = {
-                "s_method": s_method, "tuned": tuned, "ms_per_step": ms, "wall_s": wall, "ms_per_kpoint": ms / nk,
-                "tflops": sum(f_alg) / (ms * 1e-3) / 1e12,
-                "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kern.items() if v[0]},
-                "launches_per_step": {k: v[0] // args.steps for k, v in kern.items() if v[0]},
-                "contraction_tflops": achieved,
-            }
-            print(f"# {path}: {ms:.2f} ms/step, {results[path]['tflops']:.2f} TFLOP/s, kernels "
-                  f"{json.dumps(results[path]['kernels_ms_per_step'])}", flush=True)
-            if args.graph:
-                with fl.plan(cell, cell.kpts, gdev, prec=prec, slices=args.slices, out=out) as plan:
-                    plan.launch()
-                    torch.cuda.synchronize()
-                    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    g0.record(stream)
-                    for _ in range(args.steps):
-                        plan.launch(stream)
-                    g1.record(stream)
-                    torch.cuda.synchronize()
-                    results[path]["graph_ms_per_step"] = g0.elapsed_time(g1) / args.steps
-                print(f"# {path}: graph replay {results[path]['graph_ms_per_step']:.2f} ms/step", flush=True)
-            outs[path] = (out[0][0], out[0][1])       # k-point 0 is what the CPU baseline samples
+            rec.update({
+                "eager_steps": n_eager, "eager_ms_per_step": float(np.mean(per_e)),
+                "kernels_ms_per_step": {k: v[1] / n_eager for k, v in kern.items() if v[0]},
+                "launches_per_step": {k: v[0] // n_eager for k, v in kern.items() if v[0]},
+                "contraction_tflops": sum(f_contract) * n_eager / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None,
+            })
+            if notes:
+                rec["notes"] = notes
+            results[path] = rec
+            print(f"# {path}: {med:.2f} ms/step, {rec['tflops']:.2f} TFLOP/s, kernels "
+                  f"{json.dumps(rec['kernels_ms_per_step'])}", flush=True)
+            samples[path] = (gather_block(out[0][0], idx), gather_block(out[0][1], idx))
             del out
 
-    base, errs = (None, {})
+    base = None
     if not args.no_cpu_baseline:
-        base, errs = cpu_baseline_leg(cell, outs, args.cpu_sample, args.lnonsph)
+        base, (Ho, So) = cpu_baseline_leg(cell, idx, args.lnonsph)
+        ref = {"H": np.triu(Ho), "S": np.triu(So)}
         for p in precs:
-            results[p]["rel_err"] = errs[p]
+            Hs, Ss = samples[p]
+            est = {"H": error_estimates(Hs, ref["H"], cell.n_g(0)), "S": error_estimates(Ss, ref["S"], cell.n_g(0))}
+            results[p]["rel_err"] = {m: est[m]["full_relF_est"] for m in ("H", "S")}
+            results[p]["errors"] = est
+        print(f"# cpu baseline: {json.dumps(base)}", flush=True)
 
-    radial = radial_leg(cell, args.radial_nr, args.steps, not args.no_cpu_baseline) if args.radial_nr else None
+    radial = None
+    if args.radial_nr:
+        if time.perf_counter() - t_start < args.budget_s:
+            radial = radial_leg(cell, args.radial_nr, 3, not args.no_cpu_baseline)
+        else:
+            radial = {"skipped": "wall-clock guard"}
 
     head_path = precs[0]
     head, head_method = split_path(head_path)
@@ -323,31 +450,35 @@ def main():
         ex = achieved * executed_per_flop(slices, head)
         roof.update({"executed_ops_per_flop": executed_per_flop(slices, head), "executed_achieved": ex,
                      "executed_frac": ex / PEAKS[head], "slices": slices})
-    ceil = None if args.no_ceiling else mfma_ceiling()
+    ceil = mfma_ceiling() if args.ceiling else None
     if ceil:
         key = {"i8": "i8_random_TOPs", "i8mod": "i8_random_TOPs", "bf16": "bf16_random_TFLOPs",
                "fp64": "f64_random_TFLOPs"}[head]
-        ref = roof.get("executed_achieved", achieved)
+        ref_rate = roof.get("executed_achieved", achieved)
         roof["ceiling_random_operands"] = {
             "rates": ceil, "value": ceil[key],
-            "frac": (ref / ceil[key]) if ref else None,
-            "note": "matrix-core rate of a register-only loop on operands distributed like this path's "
-                    "(power-limited clock); context beside the published peak, which stays the roofline"}
+            "frac": (ref_rate / ceil[key]) if ref_rate else None,
+            "note": "matrix-core rate of a register-only loop on operands distributed like this path's; "
+                    "context beside the published peak, which stays the roofline"}
+    fp64_key = next((p for p in precs if split_path(p) == ("fp64", head_method)), None)
     line = {
         "metric": "H+S gen time/k-point & TFLOP/s: split-prec vs FP64 MFMA at ≤1e-10 rel err",
-        "value": r["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "value": r["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": r["steps"], "warmup": r["warmup"],
         "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "bf16": "bf16", "i8": "i8", "i8mod": "i8"}[head], "data": "synthetic",
-        "speedup_vs_fp64": (results["fp64"]["ms_per_step"] / r["ms_per_step"]) if "fp64" in results and head_path != "fp64" else None,
+        "speedup_vs_fp64": (results[fp64_key]["ms_per_step"] / r["ms_per_step"])
+        if fp64_key and fp64_key != head_path else None,
         "config": {"workload": cell.name, "n_atoms": cell.n_atoms, "n_types": cell.n_types, "K": kr,
                    "lmax": int(cell.lmax.max()), "lpot": cell.lpot, "n_kpoints": nk,
-                   "n_g": [cell.n_g(i) for i in range(nk)], "path": head, "slices": args.slices,
+                   "n_g": [cell.n_g(i) for i in range(nk)], "path": head, "slices": slices,
                    "s_method": head_method, "lnonsph": args.lnonsph},
         "ms_per_kpoint": r["ms_per_kpoint"],
+        "rel_err": r.get("rel_err"),
         "roofline": roof,
         "cpu_baseline": base,
         "paths": results,
         "radial_setup": radial,
+        "wall_s": time.perf_counter() - t_start,
     }
     print(json.dumps(line), flush=True)
 

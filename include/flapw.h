@@ -65,25 +65,32 @@ typedef enum {
  *               into `slices` signed digits (first in [-255, 255], later in [-128, 128]) held
  *               exactly in bfloat16; digit pairs p + q < slices run on the BF16 matrix cores
  *               and accumulate exactly in FP32 over 64 contraction rows, then are recombined
- *               and summed over atoms in FP64.
- *   SPLIT_I8    the same with int8 digits (first in [-127, 127], later in [-64, 64]) and exact
- *               int32 accumulation over 4096 rows.
- * Split precisions take 3..6 digits (FLAPW_ERR_UNSUPPORTED otherwise); 0 selects the tuned or
- * default count (6, which meets a 1e-10 relative Frobenius error on the tested workloads).
+ *               and summed over atoms in FP64.  3..6 digits.
+ *   SPLIT_FP32  two-term FP32 slices (hi = fl32(x), lo = fl32(x - hi)) with three slice products
+ *               on the FP32 matrix cores and FP32 accumulation.  Reserved and not implemented:
+ *               FP32 accumulation over the 2K contraction rows cannot reach a 1e-10 relative
+ *               error, and three FP32 products per FP64 one run below the FP64 matrix-core rate,
+ *               so every call with it returns FLAPW_ERR_UNSUPPORTED.
+ *   SPLIT_I8    the BF16 scheme with int8 digits (first in [-127, 127], later in [-64, 64]) and
+ *               exact int32 accumulation over 4096 rows.  3..6 digits.
  *   SPLIT_I8_MOD  modular split: each operand column is scaled by a power of two so that its
  *               2-norm is below 2^B and rounded to integers; the exact integer products are
  *               computed modulo `slices` pairwise coprime odd moduli <= 255 (one int8 matrix-core
  *               product per modulus, int32 accumulation) and rebuilt by the Chinese remainder
  *               theorem in FP64 (B = min(50, floor((log2 M - 1)/2)), M the product of the
- *               moduli).  Takes 8..14 moduli (FLAPW_ERR_UNSUPPORTED for 1..7); 0 selects the
- *               tuned or default count (11).  Needs, per k-point in flight, 2 `slices` bytes per
+ *               moduli).  8..14 moduli.  Needs, per k-point in flight, 2 `slices` bytes per
  *               element of each of three 2K x N operands plus 64 `slices` KiB per 128 x 128
- *               output tile of S and of H. */
+ *               output tile of S and of H.
+ * `slices` (the digit or modulus count) outside the ranges above returns FLAPW_ERR_UNSUPPORTED
+ * (FLAPW_ERR_ARG beyond FLAPW_SLICES_CAP digits or FLAPW_MODULI_CAP moduli, or below 0); 0
+ * selects the count flapw_tune chose for the same precision and problem shape, else the default
+ * (6 digits; 11 moduli). */
 typedef enum {
     FLAPW_PREC_FP64 = 0,
     FLAPW_PREC_SPLIT_BF16 = 1,
-    FLAPW_PREC_SPLIT_I8 = 2,
-    FLAPW_PREC_SPLIT_I8_MOD = 3
+    FLAPW_PREC_SPLIT_FP32 = 2,
+    FLAPW_PREC_SPLIT_I8 = 3,
+    FLAPW_PREC_SPLIT_I8_MOD = 4
 } flapw_prec;
 #define FLAPW_MODULI_CAP 14        /* largest number of moduli of FLAPW_PREC_SPLIT_I8_MOD */
 
@@ -167,8 +174,8 @@ flapw_status flapw_build_T(flapw_handle h, const flapw_radial *rad, const flapw_
  *   T    [device] as flapw_build_T writes it (must be Hermitian; it is not re-checked)
  *   H, S [device] n_g x n_g, ldh >= n_g; upper triangle written
  * `at` supplies n_atoms and type (positions and rotations are not read); `rad` supplies
- * n_types, lmax and ud_norm2.  slices: digits per operand for the split precisions
- * (3..6; 0 = tuned or library default); ignored for FP64. */
+ * n_types, lmax and ud_norm2.  slices: digits (3..6) or moduli (8..14) of the split precisions
+ * (0 = tuned or library default, see flapw_prec); ignored for FP64. */
 flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, const flapw_radial *rad,
                                const flapw_z *A, const flapw_z *B, long lda, const flapw_z *T, long ldt,
                                flapw_z *H, flapw_z *S, long ldh, flapw_prec prec, int slices,
@@ -277,22 +284,29 @@ flapw_status flapw_plan_create(flapw_handle h, int n_k, const double *k, const i
 flapw_status flapw_plan_launch(flapw_plan plan, flapw_stream stream);
 flapw_status flapw_plan_destroy(flapw_plan plan);
 
-/* Autotuner.  Chooses, for one k-point (k, n_g G vectors, device list g), the digit count of
- * the split path and the tile band of the contraction (the number of tile rows one band of the
- * launch order walks; neighbouring work-groups of a band share their row panel in L2).
- *   digits: the first min(n_g, 1024) columns are generated with FP64 and with 3, 4, 5, 6 digits;
- *           the smallest digit count whose relative Frobenius errors of H and S (upper
- *           triangles, against that FP64 result) are both <= tol / 4 is chosen.  FP64: 0.
+/* Autotuner.  Chooses, for one k-point (k, n_g G vectors, device list g), the digit or modulus
+ * count of the split path and the tile band of the contraction (the number of tile rows one band
+ * of the launch order walks; neighbouring work-groups of a band share their row panel in L2).
+ *   count:  the first n = min(n_g, 1024) columns are generated with FP64 and with 3, 4, 5, 6 digits
+ *           (SPLIT_I8, SPLIT_BF16) or 10, 11, 12, 13 moduli (SPLIT_I8_MOD).  The relative
+ *           Frobenius errors of H and S on those n x n upper triangles (against the FP64 result)
+ *           are extrapolated to the whole matrix by the factor sqrt(n_g / n): the rounding error of
+ *           every entry scales with the norms of its two operand columns, so the error mass grows
+ *           with the n_g^2 entries while the matrices' own mass sits near the diagonal and grows
+ *           with n_g.  The smallest count whose extrapolated errors are both <= tol / 2 is chosen.
+ *           FP64: 0.
  *   band:   a prefix of at most 8192 tiles of the contraction of the whole k-point is timed
  *           with HIP events for bands 1, 2, 4, 8, 16; the fastest is chosen.
- * The choice is stored in the handle under (prec, padded contraction rows of the atom set) and
- * used by later flapw_hs_contract / flapw_hs_generate / flapw_plan_create calls with slices = 0
- * (band: every call) whose atom set gives the same key.
- * Outputs: *slices, *band; digit_err[4] (errors for 3..6 digits, NaN where not evaluated) and
- * band_ms[5] (prefix times for bands 1, 2, 4, 8, 16) when not NULL.
+ * The choice is stored in the handle under (prec, padded contraction rows of the atom set as the
+ * generation lays them out, S method, lnonsph) and used by later flapw_hs_generate /
+ * flapw_plan_create calls with slices = 0 (band: every call) under the same handle settings and
+ * atom set, and by flapw_hs_contract when it was tuned with the default settings (S_GEMM, dense T).
+ * Outputs: *slices, *band; digit_err[4] (the extrapolated errors of the four candidate counts,
+ * NaN where not evaluated) and band_ms[5] (prefix times for bands 1, 2, 4, 8, 16) when not NULL.
  * Runs synchronously on the null stream and allocates temporary device memory for two n_g x n_g
  * outputs (freed before returning).  Errors: as flapw_hs_generate; FLAPW_ERR_ARG for tol <= 0;
- * FLAPW_ERR_UNSUPPORTED when no digit count meets tol (digit_err is still filled). */
+ * FLAPW_ERR_UNSUPPORTED when no candidate count meets tol (digit_err is still filled) or for
+ * FLAPW_PREC_SPLIT_FP32. */
 flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
                         const flapw_radial *rad, const flapw_potential *pot, flapw_prec prec, double tol, int *slices,
                         int *band, double *digit_err, double *band_ms);

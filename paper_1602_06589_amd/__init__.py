@@ -3,6 +3,7 @@
 The computation lives in the HIP library ``libflapw_hip.so`` (C-ABI in include/flapw.h);
 ``flapw`` is its Python binding.
 """
-from .flapw import FP64, SPLIT_BF16, SPLIT_I8, Flapw, FlapwError, Plan, hermitian_full, load_library  # noqa: F401
+from .flapw import FP64, SPLIT_BF16, SPLIT_FP32, SPLIT_I8, SPLIT_I8_MOD, Flapw, FlapwError, Plan, hermitian_full, load_library  # noqa: F401
 
-__all__ = ["Flapw", "FlapwError", "Plan", "hermitian_full", "load_library", "FP64", "SPLIT_BF16", "SPLIT_I8"]
+__all__ = ["Flapw", "FlapwError", "Plan", "hermitian_full", "load_library", "FP64", "SPLIT_BF16", "SPLIT_FP32", "SPLIT_I8",
+           "SPLIT_I8_MOD"]

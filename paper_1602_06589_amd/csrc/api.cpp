@@ -258,12 +258,16 @@ void gauss_legendre(int n, std::vector<double> &z, std::vector<double> &w)
 struct GauntPlan {
     int lt = 0, nq = 0, ls = 0, lpot = 0, n_types = 0, lnonsph = -1;
     size_t oz = 0, ow = 0, o1 = 0, o2 = 0, o3 = 0, o4 = 0, oe = 0, on = 0, ol = 0, oth = 0;
+    bool sph = false;            // also the L-diagonal T terms per (type, l), at osph (full l_max at olf)
+    size_t osph = 0, olf = 0;
 };
 
-// lnonsph >= 0: structured T; lcut >= 0: each type's row blocks stop at min(l_max, lcut).
+// lnonsph >= 0: structured T; lcut >= 0: each type's row blocks stop at min(l_max, lcut), and the
+// L-diagonal T terms of every l (needed for the rows past the cut) are formed on the device too.
 void prepare_T(const flapw_radial *rad, const flapw_potential *pot, std::vector<unsigned char> &hb, GauntPlan &gp,
                int lnonsph = -1, int lcut = -1)
 {
+    gp.sph = lcut >= 0;
     gp.lnonsph = lnonsph;
     int lm = 0;
     for (int t = 0; t < rad->n_types; ++t) lm = std::max(lm, rad->lmax[t]);
@@ -289,9 +293,12 @@ void prepare_T(const flapw_radial *rad, const flapw_potential *pot, std::vector<
     if (lcut >= 0)
         for (int &x : lrow) x = std::min(x, lcut);
     gp.ol = put(hb, lrow.data(), lrow.size());
+    gp.olf = put(hb, rad->lmax, (size_t)rad->n_types);
     gp.oth = round_up(hb.size(), 256);
     const size_t nth = (size_t)(gp.lt + 1) * (gp.lt + 2) / 2 * gp.nq;
     hb.resize(gp.oth + nth * sizeof(double));
+    gp.osph = round_up(hb.size(), 256);
+    if (gp.sph) hb.resize(gp.osph + (size_t)rad->n_types * kLStride * 4 * sizeof(double));
 }
 
 flapw_status launch_T(flapw_handle h, const unsigned char *base, const GauntPlan &gp, double2 *T, long long ldt,
@@ -305,6 +312,15 @@ flapw_status launch_T(flapw_handle h, const unsigned char *base, const GauntPlan
                     (const double *)(base + gp.o3), (const double *)(base + gp.o4), (const double *)(base + gp.oe),
                     (const double *)(base + gp.on), T, ldt, gp.lnonsph, s);
     if (e != hipSuccess) return dev_fail(h, e, "T assembly kernel");
+    if (gp.sph) {
+        e = launch_tmat_sph(gp.n_types, (const int *)(base + gp.olf), gp.ls, gp.lpot, gp.nq,
+                            (const double *)(base + gp.ow), (const double *)(base + gp.oth),
+                            (const double *)(base + gp.o1), (const double *)(base + gp.o2),
+                            (const double *)(base + gp.o3), (const double *)(base + gp.o4),
+                            (const double *)(base + gp.oe), (const double *)(base + gp.on),
+                            (double *)(const_cast<unsigned char *>(base) + gp.osph), s);
+        if (e != hipSuccess) return dev_fail(h, e, "spherical T terms kernel");
+    }
     return FLAPW_OK;
 }
 
@@ -376,6 +392,9 @@ int default_slices(flapw_prec prec) { return prec == FLAPW_PREC_SPLIT_I8_MOD ? 1
 // outside 0..FLAPW_MODULI_CAP, FLAPW_ERR_UNSUPPORTED for a count the precision does not implement.
 flapw_status check_prec(flapw_handle h, flapw_prec prec, int slices)
 {
+    if (prec == FLAPW_PREC_SPLIT_FP32)
+        return fail(h, FLAPW_ERR_UNSUPPORTED,
+                    "FP32 slices are not implemented: FP32 accumulation over the contraction cannot reach 1e-10");
     if (prec != FLAPW_PREC_FP64 && prec != FLAPW_PREC_SPLIT_BF16 && prec != FLAPW_PREC_SPLIT_I8 &&
         prec != FLAPW_PREC_SPLIT_I8_MOD)
         return fail(h, FLAPW_ERR_ARG, "unknown precision");
@@ -394,25 +413,26 @@ flapw_status check_prec(flapw_handle h, flapw_prec prec, int slices)
 // bytes per digit: int8 digits 1, bf16 digits 2
 int digit_bytes(flapw_prec prec) { return prec == FLAPW_PREC_SPLIT_BF16 ? 2 : 1; }
 
-const flapw_context::Tuned *find_tuned(flapw_handle h, flapw_prec prec, long long kp2)
+// The tuner's choice for (prec, padded contraction rows, S method, lnonsph), or NULL.
+const flapw_context::Tuned *find_tuned(flapw_handle h, flapw_prec prec, long long kp2, int s_method, int lnonsph)
 {
     for (const auto &t : h->tuned)
-        if (t.prec == (int)prec && t.kp2 == kp2) return &t;
+        if (t.prec == (int)prec && t.kp2 == kp2 && t.s_method == s_method && t.lnonsph == lnonsph) return &t;
     return nullptr;
 }
 
-// slices == 0: the tuned digit count for (prec, kp2), else the library default
-int effective_slices(flapw_handle h, flapw_prec prec, long long kp2, int slices)
+// slices == 0: the tuned digit count for the key, else the library default
+int effective_slices(flapw_handle h, flapw_prec prec, long long kp2, int s_method, int lnonsph, int slices)
 {
     if (prec == FLAPW_PREC_FP64) return 0;
     if (slices) return slices;
-    const auto *t = find_tuned(h, prec, kp2);
+    const auto *t = find_tuned(h, prec, kp2, s_method, lnonsph);
     return t && t->slices ? t->slices : default_slices(prec);
 }
 
-int effective_band(flapw_handle h, flapw_prec prec, long long kp2)
+int effective_band(flapw_handle h, flapw_prec prec, long long kp2, int s_method, int lnonsph)
 {
-    const auto *t = find_tuned(h, prec, kp2);
+    const auto *t = find_tuned(h, prec, kp2, s_method, lnonsph);
     return t ? t->band : 4;
 }
 
@@ -559,25 +579,6 @@ flapw_status run_fp64(flapw_handle h, const std::vector<ProblemDev> &probs_in, c
 }
 
 
-// The T entries that are diagonal in L, per type and l: {aa, ab, ba, bb} = the spherical term
-// (E_l, E_l ||udot||^2, 1/2, 1/2 on AA, BB, AB, BA) plus the l'' = 0 integral times
-// G_{L,L,00} = Y_00 = 1 / sqrt(4 pi) (appendix A.2, eq. t_matrices).
-void spherical_t_terms(const flapw_radial *rad, const flapw_potential *pot, std::vector<double> &out)
-{
-    const int ls = rad->lstride, nlp = (pot->lpot + 1) * (pot->lpot + 1);
-    const double y00 = 1.0 / std::sqrt(4.0 * kPi);
-    out.assign((size_t)rad->n_types * kLStride * 4, 0.0);
-    for (int t = 0; t < rad->n_types; ++t)
-        for (int l = 0; l <= rad->lmax[t]; ++l) {
-            const size_t q = (size_t)t * ls + l, ii = (q * ls + l) * nlp;
-            double *o = &out[((size_t)t * kLStride + l) * 4];
-            o[0] = rad->e_l[q] + pot->i_uu[ii] * y00;
-            o[1] = 0.5 + pot->i_ud[ii] * y00;
-            o[2] = 0.5 + pot->i_du[ii] * y00;
-            o[3] = rad->e_l[q] * rad->ud_norm2[q] + pot->i_dd[ii] * y00;
-        }
-}
-
 // ----------------------------------------------------------------------------- S/H generation plans
 
 // Everything one S/H generation over n_k k-points launches.  prepare_generate validates nothing
@@ -601,7 +602,6 @@ struct GenPlan {
     ModTable mt{};               // its moduli (mod only)
     int lnonsph = -1;            // structured T (-1: dense T)
     int lh0 = 1 << 20;           // the Legendre kernel adds to H the L-diagonal terms of l >= lh0
-    size_t ohsph = 0;            // per type and l: {aa, ab, ba, bb} of those terms
     double omega = 0.0;
     int sl = 0, band = 4;
     long long ldt = 0;
@@ -687,9 +687,10 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     p.split = prec != FLAPW_PREC_FP64;
     p.bf16 = prec == FLAPW_PREC_SPLIT_BF16;
     p.mod = prec == FLAPW_PREC_SPLIT_I8_MOD;
-    p.sl = effective_slices(h, prec, L.kp2, slices);
+    const int smeth = leg ? (int)FLAPW_S_LEGENDRE : (int)FLAPW_S_GEMM;
+    p.sl = effective_slices(h, prec, L.kp2, smeth, p.lnonsph, slices);
     if (p.mod) p.mt = make_mod_table(p.sl);
-    p.band = band ? band : effective_band(h, prec, L.kp2);
+    p.band = band ? band : effective_band(h, prec, L.kp2, smeth, p.lnonsph);
     p.ldt = 2LL * L.nlmax;
     p.pref = 4.0 * kPi / std::sqrt(at->omega);
     p.kv.assign(k, k + 3 * (size_t)n_k);
@@ -721,11 +722,6 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     p.olrow = put(ht, L.leg_row.data(), L.leg_row.size());
     p.olrng = put(ht, L.leg_ranges.data(), L.leg_ranges.size());
     p.oun2 = put(ht, L.leg_un2.data(), L.leg_un2.size());
-    if (lcut >= 0) {
-        std::vector<double> hs;
-        spherical_t_terms(rad, pot, hs);
-        p.ohsph = put(ht, hs.data(), hs.size());
-    }
     if ((st = put_device(h, *b.tables, ht, s, sync_upload)) != FLAPW_OK) return st;
     p.tables = (unsigned char *)b.tables->p;
 
@@ -869,7 +865,7 @@ flapw_status enqueue_s_legendre(flapw_handle h, const GenPlan &p, int i, double2
         e = launch_s_legendre(khat, ab, E, L.ldE, (const LegTypeRange *)(p.tables + p.olrng), p.n_types,
                               (const int *)(p.desc + p.o_stiles[i]), p.n_stiles[i], (int)p.np[i], p.ng[i],
                               4.0 * kPi / p.omega, S, lds, (const double *)(p.tables + p.oun2),
-                              with_h ? (const double *)(p.tables + p.ohsph) : nullptr,
+                              with_h ? (const double *)(p.gaunt + p.gp.osph) : nullptr,
                               p.lh0, with_h ? (double2 *)p.H[i] : nullptr, with_h ? (long long)p.ldh[i] : 0, s);
     }
     if (e != hipSuccess) return dev_fail(h, e, "Legendre S kernel");
@@ -1121,9 +1117,13 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
             if (e == hipSuccess) e = hipMemcpy((s ? Sc : Sr).data(), Sp, mat, hipMemcpyDeviceToHost);
             if (e != hipSuccess) return dev_fail(h, e, "reading tuner outputs");
             if (!s) continue;
-            const double err = std::max(upper_relfro(Hc, Hr, n_acc), upper_relfro(Sc, Sr, n_acc));
+            // extrapolated to the whole matrix: the error of an entry scales with the norms of its two
+            // operand columns, so the error mass grows with the n_g^2 entries, the matrices' own mass
+            // (near the diagonal) with n_g
+            const double err = std::max(upper_relfro(Hc, Hr, n_acc), upper_relfro(Sc, Sr, n_acc)) *
+                               std::sqrt((double)n_g / (double)n_acc);
             if (digit_err) digit_err[ci - 1] = err;
-            if (!chosen && err <= 0.25 * tol) chosen = s;
+            if (!chosen && err <= 0.5 * tol) chosen = s;
         }
         if (!chosen)
             return fail(h, FLAPW_ERR_UNSUPPORTED, prec == FLAPW_PREC_SPLIT_I8_MOD
@@ -1152,12 +1152,16 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
         if (band_ms) band_ms[i] = ms;
         if (i == 0 || ms < best_ms) best_ms = ms, best = bands[i];
     }
+    // keyed as prepare_generate looks it up: the row layout with the same cut, the S method, lnonsph
     Layout L;
-    build_layout(at, rad, true, L);
-    flapw_context::Tuned t{(int)prec, L.kp2, chosen, best};
+    int lmx = 0;
+    for (int t = 0; t < rad->n_types; ++t) lmx = std::max(lmx, rad->lmax[t]);
+    const bool leg = h->s_method == FLAPW_S_LEGENDRE;
+    build_layout(at, rad, true, L, (leg && h->lnonsph >= 0 && h->lnonsph < lmx) ? h->lnonsph : -1);
+    flapw_context::Tuned t{(int)prec, L.kp2, leg ? (int)FLAPW_S_LEGENDRE : (int)FLAPW_S_GEMM, h->lnonsph, chosen, best};
     bool found = false;
     for (auto &x : h->tuned)
-        if (x.prec == t.prec && x.kp2 == t.kp2) x = t, found = true;
+        if (x.prec == t.prec && x.kp2 == t.kp2 && x.s_method == t.s_method && x.lnonsph == t.lnonsph) x = t, found = true;
     if (!found) h->tuned.push_back(t);
     *slices = chosen;
     *band = best;
@@ -1328,9 +1332,10 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
     if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
     ProblemDev pd{P, Q, (const double *)(base + od), (double2 *)H, (double2 *)S, L.kp2, ldh, n_g, (int)L.kp2};
     std::vector<int> npt{(int)(np / kTile)};
-    const int band = effective_band(h, prec, L.kp2);
+    // T is taken as given and S from the matrix cores: the key of the default handle settings
+    const int band = effective_band(h, prec, L.kp2, FLAPW_S_GEMM, -1);
     if (prec == FLAPW_PREC_FP64) return run_fp64(h, {pd}, npt, band, s);
-    const int sl = effective_slices(h, prec, L.kp2, slices);
+    const int sl = effective_slices(h, prec, L.kp2, FLAPW_S_GEMM, -1, slices);
     if (prec == FLAPW_PREC_SPLIT_I8_MOD) {
         e = h->digits.ensure((size_t)mod_area_bytes(L.kp2, np, sl));
         if (e != hipSuccess) return dev_fail(h, e, "allocating residue buffer");

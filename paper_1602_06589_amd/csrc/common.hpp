@@ -88,6 +88,9 @@ hipError_t launch_tmat(int n_types, const int *lmax_dev, int lstride, int lpot, 
                        const double *theta, const double *i_uu, const double *i_ud, const double *i_du,
                        const double *i_dd, const double *e_l, const double *ud_norm2, double2 *T, long long ldt,
                        int lnonsph, hipStream_t s);
+hipError_t launch_tmat_sph(int n_types, const int *lmax_dev, int lstride, int lpot, int nq, const double *w,
+                           const double *theta, const double *i_uu, const double *i_ud, const double *i_du,
+                           const double *i_dd, const double *e_l, const double *ud_norm2, double *out, hipStream_t s);
 
 // Q_a = T_type(a) P_a for every atom; rows from the end of the last atom block up to kp2 are set
 // to zero.  real_t: T is known to be real (built by the library from real integrals): half the MFMAs

@@ -65,10 +65,13 @@ struct flapw_context {
     int lnonsph = -1;          // structured T (flapw_set_lnonsph); -1: dense T
     std::vector<unsigned char> host_tables, host_gaunt, host_tiles, host_sdesc;
     std::vector<long long> host_src;
-    // tuning (flapw_tune): chosen digit count and tile band per (precision, padded contraction rows)
+    // tuning (flapw_tune): chosen digit count and tile band per (precision, padded contraction rows,
+    // S method, lnonsph)
     struct Tuned {
         int prec;
         long long kp2;
+        int s_method;
+        int lnonsph;
         int slices;
         int band;
     };

@@ -97,7 +97,46 @@ __global__ void tmat_kernel(int n_types, const int *lmax_t, int lstride, int lpo
     *out = make_double2(s, 0.0);
 }
 
+// The T entries that are diagonal in L, per (type, l) for l <= l_max of the type (lmax_t: the
+// full l_max, not a cut row block): out[(ty * kLStride + l) * 4 + {0, 1, 2, 3}] = {aa, ab, ba, bb},
+// the spherical terms (E_l, 1/2, 1/2, E_l ||udot||^2, eq. t_matrices) plus the l'' = 0 integrals
+// times G_{L,L,00} (the same quadrature as tmat_kernel; it equals Y_00 for every m).  Entries past
+// l_max are zero.  The addition-theorem kernel adds these to H for the rows a structured T leaves
+// out of the contraction.
+__global__ void tmat_sph_kernel(int n_types, const int *lmax_t, int lstride, int lpot, int nq, const double *w,
+                                const double *theta, const double *i_uu, const double *i_ud, const double *i_du,
+                                const double *i_dd, const double *e_l, const double *ud_norm2, double *out)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_types * kLStride) return;
+    const int ty = idx / kLStride, l = idx % kLStride;
+    double *o = out + (long long)idx * 4;
+    if (l > lmax_t[ty]) {
+        o[0] = o[1] = o[2] = o[3] = 0.0;
+        return;
+    }
+    double gq = 0.0;
+    for (int i = 0; i < nq; ++i) gq += w[i] * theta_at(theta, nq, l, 0, i) * theta_at(theta, nq, l, 0, i) * theta_at(theta, nq, 0, 0, i);
+    const double g = 2.0 * kPi * gq;
+    const int nlp = (lpot + 1) * (lpot + 1);
+    const long long q = (long long)ty * lstride + l, ii = (q * lstride + l) * nlp;
+    o[0] = e_l[q] + i_uu[ii] * g;
+    o[1] = 0.5 + i_ud[ii] * g;
+    o[2] = 0.5 + i_du[ii] * g;
+    o[3] = e_l[q] * ud_norm2[q] + i_dd[ii] * g;
+}
+
 }  // namespace
+
+hipError_t launch_tmat_sph(int n_types, const int *lmax_dev, int lstride, int lpot, int nq, const double *w,
+                           const double *theta, const double *i_uu, const double *i_ud, const double *i_du,
+                           const double *i_dd, const double *e_l, const double *ud_norm2, double *out, hipStream_t s)
+{
+    const int n = n_types * kLStride;
+    hipLaunchKernelGGL(tmat_sph_kernel, dim3((n + 63) / 64), dim3(64), 0, s, n_types, lmax_dev, lstride, lpot, nq, w,
+                       theta, i_uu, i_ud, i_du, i_dd, e_l, ud_norm2, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_legendre_table(int lt, int nq, const double *z, double *theta, hipStream_t s)
 {

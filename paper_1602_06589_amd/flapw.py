@@ -26,8 +26,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libflapw_hip.so")
 
-FP64, SPLIT_BF16, SPLIT_I8, SPLIT_I8_MOD = 0, 1, 2, 3
-PRECISIONS = {"fp64": FP64, "bf16": SPLIT_BF16, "i8": SPLIT_I8, "i8mod": SPLIT_I8_MOD}
+FP64, SPLIT_BF16, SPLIT_FP32, SPLIT_I8, SPLIT_I8_MOD = 0, 1, 2, 3, 4
+PRECISIONS = {"fp64": FP64, "bf16": SPLIT_BF16, "fp32": SPLIT_FP32, "i8": SPLIT_I8, "i8mod": SPLIT_I8_MOD}
 S_METHODS = {"gemm": 0, "legendre": 1}
 
 _STATUS = {0: "FLAPW_OK", -1: "FLAPW_ERR_ARG", -2: "FLAPW_ERR_WRONSKIAN", -3: "FLAPW_ERR_NOT_HERMITIAN",

@@ -156,18 +156,48 @@ def test_plan_validation(handle):
     assert handle._lib.flapw_plan_create(*_gen_args(handle, cell, n_g=0), 0, 0, ctypes.byref(out)) == -1
     assert out.value is None                                          # cleared on failure
     assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 1, 2, ctypes.byref(out)) == -6
-    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 2, 7, ctypes.byref(out)) == -6
-    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 4, 0, ctypes.byref(out)) == -1
-    # modular split: 8..14 moduli; 1..7 unsupported, beyond the cap an argument error
     assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 3, 7, ctypes.byref(out)) == -6
-    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 3, 15, ctypes.byref(out)) == -1
-    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 3, -1, ctypes.byref(out)) == -1
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 5, 0, ctypes.byref(out)) == -1
+    # modular split: 8..14 moduli; 1..7 unsupported, beyond the cap an argument error
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 4, 7, ctypes.byref(out)) == -6
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 4, 15, ctypes.byref(out)) == -1
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 4, -1, ctypes.byref(out)) == -1
     assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 0, 0, None) == -1
     assert handle._lib.flapw_plan_launch(None, None) == -1
     assert handle._lib.flapw_plan_destroy(None) == -1
 
 
-def _call_tune(f, cell, tol, prec=2, n_g=None):
+def test_precision_enum(handle, lib):
+    """flapw_prec as the boundary names it: 0 FP64, 1 SPLIT_BF16, 2 SPLIT_FP32 (reserved: every call
+    returns FLAPW_ERR_UNSUPPORTED), 3 SPLIT_I8, 4 SPLIT_I8_MOD; anything else is an argument error.
+    Valid precisions pass validation (without a device they stop at the device check)."""
+    import torch
+    from paper_1602_06589_amd import flapw as F
+    assert (F.FP64, F.SPLIT_BF16, F.SPLIT_FP32, F.SPLIT_I8, F.SPLIT_I8_MOD) == (0, 1, 2, 3, 4)
+    cell = synthcells.config(0)
+    gen = lambda prec, sl=0: lib.flapw_hs_generate(*_gen_args(handle, cell), prec, sl, None)
+    assert gen(2) == -6 and gen(2, 2) == -6
+    assert b"FP32" in lib.flapw_last_error(handle._h)
+    out = ctypes.c_void_p()
+    assert lib.flapw_plan_create(*_gen_args(handle, cell), 2, 0, ctypes.byref(out)) == -6
+    assert _call_tune(handle, cell, 1e-10, prec=2)[0] == -6
+    for bad in (-1, 5, 99):
+        assert gen(bad) == -1
+    if not torch.cuda.is_available():
+        for good in (0, 1, 3, 4):
+            assert gen(good) == -5
+    # counts: digits 3..6 for 1 and 3, moduli 8..14 for 4
+    assert gen(1, 7) == -6 and gen(3, 2) == -6 and gen(4, 7) == -6 and gen(4, 15) == -1
+    # flapw_hs_contract rejects the reserved precision before touching its (stand-in) pointers
+    handle._keep = []
+    rad, at = handle._radial(cell), handle._atoms(cell)
+    P = ctypes.c_void_p
+    n, kr = cell.n_g(0), cell.k_rows()
+    assert lib.flapw_hs_contract(handle._h, n, ctypes.byref(at), ctypes.byref(rad), P(0x1000), P(0x2000), kr,
+                                 P(0x3000), 2 * 49, P(0x4000), P(0x5000), n, 2, 0, None) == -6
+
+
+def _call_tune(f, cell, tol, prec=3, n_g=None):
     from paper_1602_06589_amd import flapw as F
     f._keep = []
     rad, at, pot = f._radial(cell), f._atoms(cell), f._potential(cell)
@@ -186,6 +216,7 @@ def test_tune_validation(handle):
     assert _call_tune(handle, cell, float("nan"))[0] == -1
     assert _call_tune(handle, cell, 1e-10, n_g=0)[0] == -1
     assert _call_tune(handle, cell, 1e-10, prec=5)[0] == -1
+    assert _call_tune(handle, cell, 1e-10, prec=2)[0] == -6           # FP32 slices: reserved
     bad = synthcells.config(0)
     bad.i_uu[0, 2, 3, 5] += 1e-3
     assert _call_tune(handle, bad, 1e-10)[0] == -3
@@ -197,7 +228,7 @@ def test_plan_and_tune_no_device(handle):
         pytest.skip("a GPU is present")
     cell = synthcells.config(0)
     out = ctypes.c_void_p()
-    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 2, 0, ctypes.byref(out)) == -5
+    assert handle._lib.flapw_plan_create(*_gen_args(handle, cell), 3, 0, ctypes.byref(out)) == -5
     st, sl, band = _call_tune(handle, cell, 1e-10)
     assert st == -5 and sl == -1 and band == -1                       # outputs untouched on failure
 

@@ -1,6 +1,7 @@
 """bench.py host logic, on the CPU: the refusal of more than one GPU, the refusal without a GPU,
-the counter-summary lookup that fills the roofline's traffic (and its invalidation when the
-kernel source changes), and the executed-operation factors of the split paths."""
+the default paths and step caps, the unbiased full-matrix error estimate, the counter-summary
+lookup that fills the roofline's traffic (and its invalidation when the kernel source changes),
+and the executed-operation factors of the split paths."""
 import hashlib
 import os
 import subprocess
@@ -60,3 +61,41 @@ def test_traffic_line_is_read_for_the_current_source(tmp_path, monkeypatch):
 def test_executed_operations_per_flop(prec, slices, factor):
     """One int8 product per modulus; s(s+1)/2 digit-pair products for the digit schemes."""
     assert bench.executed_per_flop(slices, prec) == factor
+
+
+def test_default_paths_and_step_caps():
+    """Default run: the modular split headline and the FP64 comparator only, no matrix-core probe;
+    the headline takes the requested steps, every other path at most 1 warm-up and 3 timed steps."""
+    a = bench.make_parser().parse_args([])
+    assert a.precs == "i8mod,fp64" and a.config == 4 and a.gpus == 1
+    assert not a.ceiling and not a.eager
+    assert a.steps >= 10 and a.warmup >= 3
+    assert bench.step_plan(True, 20, 5) == (5, 20, 3)
+    assert bench.step_plan(False, 20, 5) == (1, 3, 1)
+    assert bench.step_plan(False, 2, 0) == (0, 2, 1)
+    assert bench.step_plan(True, 1, 0) == (0, 1, 1)
+
+
+def test_error_estimate_reweights_the_sample():
+    """A random principal submatrix of n of N indices: the estimate weighs its diagonal by N/n and
+    its pairs by N(N-1)/(n(n-1)); on a matrix whose error and value are uniform per class (diagonal,
+    off-diagonal) it returns the whole matrix's relative Frobenius error exactly."""
+    import numpy as np
+    n, N = 50, 2000
+    ref = np.full((n, n), 0.01, complex)
+    np.fill_diagonal(ref, 1.0)
+    err = np.full((n, n), 1e-12, complex)
+    np.fill_diagonal(err, 1e-13)
+    got = np.triu(ref + err)
+    e = bench.error_estimates(got, np.triu(ref), N)
+    full_err2 = N * 1e-26 + N * (N - 1) * 1e-24
+    full_ref2 = N * 1.0 + N * (N - 1) * 1e-4
+    assert abs(e["full_relF_est"] - np.sqrt(full_err2 / full_ref2)) < 1e-5 * e["full_relF_est"]   # rounding of ref + err
+    # the sample's own error under-weights the off-diagonal error: the estimate is larger here
+    assert e["full_relF_est"] > 2 * e["sample_relF"]
+    assert abs(e["max_err_over_max"] - 1e-12) < 1e-17
+    # a sample that is the whole matrix gives its own (Hermitian, full) error
+    e2 = bench.error_estimates(got, np.triu(ref), n)
+    full = lambda U: U + np.triu(U, 1).conj().T
+    direct = np.linalg.norm(full(got) - ref) / np.linalg.norm(ref)
+    assert abs(e2["full_relF_est"] - direct) < 1e-9 * direct

@@ -128,7 +128,8 @@ def test_tune_digits_and_use(ctx, oracle_lib):
             errs = res["digit_err"]
             assert all(math.isfinite(e) for e in errs)
             assert all(errs[i + 1] < errs[i] for i in range(3)), errs
-            assert errs[s - 3] <= tol / 4 and (s == 3 or errs[s - 4] > tol / 4), res
+            # n_g <= 1024: the tuner's sample is the whole matrix (extrapolation factor 1)
+            assert errs[s - 3] <= tol / 2 and (s == 3 or errs[s - 4] > tol / 2), res
             assert all(math.isfinite(t) and t > 0 for t in res["band_ms"]), res
             # slices = 0 now means the tuned count: bitwise equal to asking for it explicitly
             (H0, S0), = f.hs_generate(cell, cell.kpts, [g], prec="i8")
@@ -155,7 +156,7 @@ def test_tune_fp64_and_unreachable(ctx):
 
 
 def test_tune_moduli_and_use(ctx, oracle_lib):
-    """Modular split: the tuner picks the smallest of 10..13 moduli meeting tol / 4."""
+    """Modular split: the tuner picks the smallest of 10..13 moduli meeting tol / 2."""
     from paper_1602_06589_amd import Flapw
     cell = _mixed(seed=46, n_g=300, n_k=1)
     g = _dev(cell.gvecs[0])
@@ -166,7 +167,7 @@ def test_tune_moduli_and_use(ctx, oracle_lib):
         errs = res["digit_err"]
         assert 10 <= s <= 13 and res["band"] in (1, 2, 4, 8, 16), res
         assert all(math.isfinite(e) for e in errs)
-        assert errs[s - 10] <= 2.5e-11 and (s == 10 or errs[s - 11] > 2.5e-11), res
+        assert errs[s - 10] <= 5e-11 and (s == 10 or errs[s - 11] > 5e-11), res
         assert all(errs[i + 1] < errs[i] for i in range(2)), errs
         (H0, S0), = f.hs_generate(cell, cell.kpts, [g], prec="i8mod")
         (H1, S1), = f.hs_generate(cell, cell.kpts, [g], prec="i8mod", slices=s)
@@ -175,3 +176,29 @@ def test_tune_moduli_and_use(ctx, oracle_lib):
         assert np.array_equal(S0.cpu().numpy()[up], S1.cpu().numpy()[up])
         assert _relfro(_upper(H0.cpu().numpy()), Ho) < 1e-10
         assert _relfro(_upper(S0.cpu().numpy()), So) < 1e-10
+
+
+def test_tuned_count_used_with_legendre_s_and_structured_t(ctx):
+    """The tuner's choice is found again by generations under the same handle settings, also when S
+    comes from the addition theorem and a structured T cuts the contraction rows (the layout the
+    choice is keyed on is the cut one), and not under other settings."""
+    from paper_1602_06589_amd import Flapw
+    cell = _mixed(seed=47, n_g=260, n_k=1)
+    g = _dev(cell.gvecs[0])
+    up = _upper_mask(cell.n_g(0))
+    with Flapw() as f:
+        f.set_s_method("legendre")
+        f.set_lnonsph(2)
+        res = f.tune(cell, cell.kpts[0], g, prec="i8mod", tol=1e-4)       # loose: the smallest candidate
+        assert res["slices"] == 10, res
+        (H0, _), = f.hs_generate(cell, cell.kpts, [g], prec="i8mod")
+        (H10, _), = f.hs_generate(cell, cell.kpts, [g], prec="i8mod", slices=10)
+        (H11, _), = f.hs_generate(cell, cell.kpts, [g], prec="i8mod", slices=11)
+        h0, h10, h11 = (x.cpu().numpy()[up] for x in (H0, H10, H11))
+        assert np.array_equal(h0, h10)
+        assert not np.array_equal(h0, h11)                               # 11 moduli: the default
+        f.set_lnonsph(-1)                                                # another key: the default again
+        f.set_s_method("gemm")
+        (Hd, _), = f.hs_generate(cell, cell.kpts, [g], prec="i8mod")
+        (Hd11, _), = f.hs_generate(cell, cell.kpts, [g], prec="i8mod", slices=11)
+        assert np.array_equal(Hd.cpu().numpy()[up], Hd11.cpu().numpy()[up])
