@@ -14,6 +14,9 @@ this module only marshals numpy arrays through ctypes.  Functions:
   coeffs(cell, ik, cols)       A_*, B_* (K x n)                      appendix A.1, eqs. def_a/def_b
   hs_block(cell, ...)          blocks of H and S                     section 2.3, eqs. def_overlap,
                                                                      def_hamilton
+  interstitial_block(cell, ..) interstitial blocks of H and S        section 2.3, eqs. basis_function
+                                                                     (INT), HS_Mat
+  eigh_generalized(H, S)       H c = eps S c                         section 2.3, eq. matrix_kohnsham
 """
 from __future__ import annotations
 
@@ -62,6 +65,7 @@ def _load():
             lib.or_coeffs.argtypes = [I, P, P, P, D, I, P, P, P, P, P, P, P, I, P, P, P, L]
             lib.or_hs_block.argtypes = [I, P, P, I, P, P, I, I, L, I, P, P, L, I, P, P, L, P, P]
             lib.or_radial.argtypes = [I, D, D, P, I, D, P, P, P]
+            lib.or_interstitial_block.argtypes = [I, P, P, P, D, D, P, I, P, I, P, P, P]
             lib.or_radial_integral.argtypes = [I, D, D, P, P, P]
             lib.or_radial_integral.restype = D
             _lib = lib
@@ -178,6 +182,38 @@ def hs_sampled(cell, ik: int, rows, cols, T=None):
     Al, Bl = coeffs(cell, ik, rows)
     Ar, Br = coeffs(cell, ik, cols)
     return hs_block(cell, T, Al, Bl, Ar, Br)
+
+
+def interstitial_block(cell, ik: int, rows=None, cols=None, v_int: float = 0.0):
+    """Interstitial H and S (plane waves integrated over the cell minus the muffin-tin spheres) for
+    the basis functions `rows` (bra) and `cols` (ket) of k-point ik (default: all).  Returns (H, S)
+    as (nr x nc) arrays."""
+    g = cell.gvecs[ik]
+    gr = _c(g if rows is None else g[np.asarray(rows)], np.float64)
+    gc = _c(g if cols is None else g[np.asarray(cols)], np.float64)
+    nr, nc = gr.shape[0], gc.shape[0]
+    H = np.zeros((nc, nr), dtype=np.complex128)
+    S = np.zeros((nc, nr), dtype=np.complex128)
+    _load().or_interstitial_block(cell.n_atoms, _p(_c(cell.atom_type, np.int32)), _p(_c(cell.rmt, np.float64)),
+                                  _p(_c(cell.pos, np.float64)), float(cell.omega), float(v_int),
+                                  _p(_c(cell.kpts[ik], np.float64)), nr, _p(gr), nc, _p(gc), _p(H), _p(S))
+    return H.T, S.T
+
+
+def hs_total(cell, ik: int, v_int: float = 0.0, lnonsph: int = -1):
+    """Full N x N H and S of one k-point including the interstitial region (muffin-tin part of
+    hs_full plus interstitial_block); small problems only."""
+    Hm, Sm = hs_full(cell, ik, lnonsph=lnonsph)
+    Hi, Si = interstitial_block(cell, ik, v_int=v_int)
+    return Hm + Hi, Sm + Si
+
+
+def eigh_generalized(H, S):
+    """Eigenvalues (ascending) and S-orthonormal eigenvectors of H c = eps S c (section 2.3, eq.
+    matrix_kohnsham) for Hermitian H and positive definite S, by the library routine
+    scipy.linalg.eigh (full matrices, both triangles given)."""
+    import scipy.linalg
+    return scipy.linalg.eigh(H, S)
 
 
 # ----------------------------------------------------------------------------- radial functions

@@ -306,6 +306,56 @@ void or_hs_block(int n_atoms, const int *type, const int *lmax_t, int lstride, c
 }
 
 /* ---------------------------------------------------------------------------------------
+ * Interstitial S and H of one block (section 2.3: eq. HS_Mat over the region outside the
+ * muffin-tin spheres, where eq. basis_function makes every basis function the plane wave
+ * exp(i K_t . r) / sqrt(Omega)):
+ *   S^I_{t',t} = (1/Omega) int_{cell minus spheres} exp(i G . r) dr,   G = K_t - K_t'
+ *             = delta_{G,0} - sum_a (1/Omega) int_{|r - x_a| < R_a} exp(i G . r) dr
+ *             = delta_{G,0} - sum_a exp(i G . x_a) (4 pi R_a^3 / Omega) j_1(|G| R_a) / (|G| R_a)
+ * (the cell integral of a plane wave of a reciprocal lattice vector G vanishes unless G = 0, and
+ * the integral over a ball is 4 pi int_0^R j_0(|G| s) s^2 ds = 4 pi R^2 j_1(|G| R) / |G|, with the
+ * limit 4 pi R^3 / 3 at G = 0).  The spheres must not overlap.
+ *   H^I_{t',t} = (1/2 K_t' . K_t + v_int) S^I_{t',t}
+ * (kinetic energy in the symmetric form (1/2) int grad conj(phi_t') . grad phi_t, and a constant
+ * interstitial potential v_int).  Bra rows gr (nr x 3), ket columns gc (nc x 3), Cartesian G;
+ * K = k + G.  Output blocks H, S: nr x nc, column-major.
+ * ------------------------------------------------------------------------------------- */
+void or_interstitial_block(int n_atoms, const int *type, const double *rmt, const double *pos, double omega,
+                           double v_int, const double *kvec, int nr, const double *gr, int nc, const double *gc,
+                           zc *H, zc *S)
+{
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < nc; ++c) {
+        for (int r = 0; r < nr; ++r) {
+            double G[3], kb[3], kk[3];
+            for (int i = 0; i < 3; ++i) {
+                G[i] = gc[3 * c + i] - gr[3 * r + i];
+                kb[i] = kvec[i] + gr[3 * r + i];
+                kk[i] = kvec[i] + gc[3 * c + i];
+            }
+            double gn = sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
+            zc s = (gn == 0.0) ? 1.0 : 0.0;
+            for (int a = 0; a < n_atoms; ++a) {
+                double R = rmt[type[a]];
+                double ball;                               /* (1/Omega) int over the ball at the origin */
+                if (gn == 0.0) {
+                    ball = 4.0 * M_PI * R * R * R / (3.0 * omega);
+                } else {
+                    double j[2], dj[2];
+                    or_sph_bessel(1, gn * R, j, dj);
+                    ball = 4.0 * M_PI * R * R * j[1] / (gn * omega);
+                }
+                double gx = G[0] * pos[3 * a] + G[1] * pos[3 * a + 1] + G[2] * pos[3 * a + 2];
+                s -= cexp(I * gx) * ball;
+            }
+            double kin = 0.5 * (kb[0] * kk[0] + kb[1] * kk[1] + kb[2] * kk[2]);
+            S[(size_t)c * nr + r] = s;
+            H[(size_t)c * nr + r] = (kin + v_int) * s;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------------------
  * Radial functions (section 2.2, eq. simp_Schr) and the non-spherical radial integrals
  * (appendix A.2, eq. nonsph_integrals), in Hartree atomic units (hbar = m = 1, so the
  * kinetic prefactor is 1/2):

@@ -37,7 +37,7 @@ from typing import List, Optional
 
 import numpy as np
 
-__all__ = ["Cell", "config", "custom_cell", "kset", "random_contraction_inputs", "radial_meshes", "RadialMeshes",
+__all__ = ["Cell", "config", "config_separated", "custom_cell", "kset", "random_contraction_inputs", "radial_meshes", "RadialMeshes",
            "CONFIG_NAMES"]
 
 CONFIG_NAMES = ["c0_small", "c1_realistic", "c2_precision", "c3_batched", "c4_scale"]
@@ -285,6 +285,37 @@ def config(i: int, n_k: Optional[int] = None) -> Cell:
     else:
         raise ValueError(f"unknown config {i}")
     return cell
+
+
+def min_sphere_gap(cell: Cell) -> float:
+    """Smallest distance between two muffin-tin spheres over the periodic images (negative when two
+    overlap): min over atom pairs of |x_b - x_a| (minimum image) - R_a - R_b."""
+    inv = np.linalg.inv(cell.lattice)
+    R = cell.rmt[cell.atom_type]
+    gap = np.inf
+    for a in range(cell.n_atoms):
+        d = cell.pos - cell.pos[a]
+        f = d @ inv
+        f -= np.round(f)
+        dist = np.linalg.norm(f @ cell.lattice, axis=1)
+        dist[a] = np.inf
+        gap = min(gap, float(np.min(dist - R - R[a])))
+    return gap
+
+
+def config_separated(i: int, n_k: Optional[int] = None) -> Cell:
+    """A named workload whose muffin-tin spheres do not overlap, as the interstitial region needs.
+    Workloads 1-4 already qualify and are returned as they are; workload 0 (two atoms at random
+    positions, whose spheres overlap) keeps its cell, type, l_max, radial data, k-point and basis,
+    with its positions redrawn (seeded) until the spheres are at least 0.5 bohr apart."""
+    cell = config(i, n_k)
+    if i != 0:
+        return cell
+    rng = _rng([1602, 6589, 0, 7])
+    while True:
+        cell.pos = rng.uniform(0.0, 1.0, size=(cell.n_atoms, 3)) * cell.lattice[0, 0]
+        if min_sphere_gap(cell) >= 0.5:
+            return cell
 
 
 def random_contraction_inputs(seed, k_rows: int, n_g: int):
