@@ -65,9 +65,10 @@ def kernel_sources_sha(prec: str) -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(prec: str, workload: str):
+def read_traffic(prec: str, workload: str, slices: int = 0):
     """HBM bytes per launch of the contraction kernel from the committed rocprofv3 counter summary,
-    or None when the kernel source changed since the counters were taken."""
+    or None when the kernel source changed since the counters were taken (or, for a line that names
+    its digit or modulus count, when the count differs)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     sha = kernel_sources_sha(prec)
@@ -75,7 +76,8 @@ def read_traffic(prec: str, workload: str):
         if not line.startswith("traffic "):
             continue
         kv = dict(x.split("=", 1) for x in line.split()[1:])
-        if kv.get("kernel") == KERNEL[prec] and kv.get("workload") == workload and kv.get("src_sha") == sha:
+        if kv.get("kernel") == KERNEL[prec] and kv.get("workload") == workload and kv.get("src_sha") == sha \
+                and ("slices" not in kv or int(kv["slices"]) == slices):
             return float(kv["bytes_per_launch"])
     return None
 
@@ -247,7 +249,8 @@ def make_parser() -> argparse.ArgumentParser:
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner and use the library's default digit or modulus count and tile "
                          "band (by default each split path is tuned on k-point 0 before timing)")
-    ap.add_argument("--cpu-sample", type=int, default=384)
+    ap.add_argument("--cpu-sample", type=int, default=768,
+                    help="basis functions of k-point 0 in the oracle's random principal submatrix")
     ap.add_argument("--radial-nr", type=int, default=1001,
                     help="mesh points of the radial-setup leg (radial functions and integrals of the "
                          "workload's atom types); 0 skips the leg")
@@ -434,8 +437,8 @@ def main():
     k_ms = r["kernels_ms_per_step"].get(KERNEL[head], 0.0) / n_launch
     achieved = r["contraction_tflops"]
     # the committed counters cover the default method (S with H on the matrix cores)
-    traffic = read_traffic(head, cell.name) if head_method == "gemm" else None
     slices = args.slices or ((r["tuned"] or {}).get("slices") or DEFAULT_SLICES.get(head, 0))
+    traffic = read_traffic(head, cell.name, slices) if head_method == "gemm" else None
     roof = {"bound": "mfma", "kernel": KERNEL[head], "achieved": achieved, "peak": PEAKS[head],
             "unit": "TFLOP/s" if head == "fp64" else "TOP/s",
             "frac": (achieved / PEAKS[head]) if achieved else None, "traffic": traffic,

@@ -55,7 +55,9 @@ typedef enum {
     FLAPW_ERR_NOT_HERMITIAN = -3,  /* non-spherical integrals would make T non-Hermitian */
     FLAPW_ERR_NOMEM = -4,          /* device work buffer allocation failed */
     FLAPW_ERR_DEVICE = -5,         /* a HIP call failed */
-    FLAPW_ERR_UNSUPPORTED = -6     /* request outside what the library implements */
+    FLAPW_ERR_UNSUPPORTED = -6,    /* request outside what the library implements */
+    FLAPW_ERR_NOT_POSDEF = -7,     /* flapw_eigensolve: S is not positive definite */
+    FLAPW_ERR_NO_CONVERGENCE = -8  /* flapw_eigensolve: the tridiagonal eigensolver did not converge */
 } flapw_status;
 
 /* Arithmetic of the S and H contractions.  Coefficients, T and the per-atom panels T_a P_a
@@ -181,6 +183,27 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
                                flapw_z *H, flapw_z *S, long ldh, flapw_prec prec, int slices,
                                flapw_stream stream);
 
+/* flapw_hs_contract for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same arguments, kernels and results (bit
+ * for bit), but every work buffer (the P and Q panels, digits or residues, descriptors) is carved
+ * out of one static device array of flapw_noalloc_scratch_bytes() bytes (64 MiB) per device,
+ * which the device holds from the load of the library until the process ends.  The call makes
+ * no hipMalloc / hipFree and allocates nothing else on the device; descriptors reach the array by
+ * hipMemcpyAsync from the handle's host buffers.  Every call on a device shares that device's
+ * array and leaves its contents behind (the kernels write every byte they read, so nothing needs
+ * clearing); calls that overlap on one device -- from two streams or two threads, through any
+ * handle -- race on it and must be serialised by the caller.  Errors: as flapw_hs_contract;
+ * FLAPW_ERR_ARG (nothing launched) when the problem needs more than the array holds (about
+ * 2 * roundup(2K, 256) * roundup(n_g, 64) * 16 bytes of panels plus, for the split precisions,
+ * their digits or residues); FLAPW_ERR_DEVICE when the array's address could not be found at
+ * flapw_create. */
+flapw_status flapw_hs_contract_noalloc(flapw_handle h, int n_g, const flapw_atoms *at, const flapw_radial *rad,
+                                       const flapw_z *A, const flapw_z *B, long lda, const flapw_z *T, long ldt,
+                                       flapw_z *H, flapw_z *S, long ldh, flapw_prec prec, int slices,
+                                       flapw_stream stream);
+/* Size of that per-device array in bytes. */
+long long flapw_noalloc_scratch_bytes(void);
+
 /* The whole path for n_k k-points (one H and one S per k-point, section 2.3): coefficients,
  * T, per-atom panels and the S/H contractions, all k-points of a memory batch in one grouped
  * launch of the contraction kernel.
@@ -225,6 +248,49 @@ flapw_status flapw_set_lnonsph(flapw_handle h, int lnonsph);
  * Errors: FLAPW_ERR_ARG, FLAPW_ERR_WRONSKIAN, FLAPW_ERR_DEVICE (as flapw_coeffs). */
 flapw_status flapw_s_legendre(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
                               const flapw_radial *rad, flapw_z *S, long lds, flapw_stream stream);
+
+/* Interstitial parts of S and H of one k-point (section 2.3: eq. HS_Mat over the cell minus the
+ * muffin-tin spheres, where eq. basis_function makes every basis function the plane wave
+ * exp(i K_t.r) / sqrt(Omega)), ADDED to the upper triangles of S and H:
+ *     S^I_{t',t} = delta_{t't} - sum_a exp(i G.x_a) (4 pi R_a^3 / Omega) j_1(|G| R_a) / (|G| R_a)
+ *     H^I_{t',t} = (K_t'.K_t / 2 + v_int) S^I_{t',t},        G = K_t - K_t',
+ * i.e. the plane-wave overlap over the cell minus the balls, the kinetic energy in its symmetric
+ * form (1/2) int grad conj(phi_t') . grad phi_t over that region, and a constant interstitial
+ * potential v_int (hartree).  With the muffin-tin parts of flapw_hs_generate these make the full
+ * S (positive definite) and H of eq. matrix_kohnsham.  FP64; the atom sum runs per atom type as
+ * a phase product on the FP64 matrix cores.
+ *   k [host] 3 doubles; g [device] n_g x 3 Cartesian G; at (positions, omega) and rad (n_types,
+ *   rmt; validated as for flapw_coeffs) as elsewhere; lattice [host] 3 x 3 row-major lattice
+ *   vectors (bohr), used only to check that no two spheres overlap among the nearest periodic
+ *   images (|det| must match omega to 1e-9 relative).
+ *   H, S [device] n_g x n_g column-major, ldh >= n_g: the terms are added on the upper triangle
+ *   (diagonal imaginary parts set to 0); the strictly lower part is untouched.
+ * Errors: FLAPW_ERR_ARG (also for overlapping spheres or a lattice that does not match omega),
+ * FLAPW_ERR_WRONSKIAN, FLAPW_ERR_NOMEM, FLAPW_ERR_DEVICE. */
+flapw_status flapw_interstitial(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
+                                const flapw_radial *rad, const double *lattice, double v_int, flapw_z *H,
+                                flapw_z *S, long ldh, flapw_stream stream);
+
+/* Handle setting: with on != 0, flapw_hs_generate and flapw_plan_create add the interstitial
+ * terms of flapw_interstitial (same lattice check, potential v_int) to every k-point's H and S
+ * after the muffin-tin parts, so that the outputs are the full matrices of eq. matrix_kohnsham.
+ * lattice [host] as for flapw_interstitial (copied; may be NULL when on == 0).  Default: off.
+ * Errors: FLAPW_ERR_ARG (NULL lattice with on != 0, non-finite v_int). */
+flapw_status flapw_set_interstitial(flapw_handle h, int on, const double *lattice, double v_int);
+
+/* Generalized Hermitian eigenproblem H c = eps S c of one k-point (section 2.3, eq.
+ * matrix_kohnsham; the eigensolve step of the self-consistency cycle), in place and in FP64:
+ * S = U^H U (Cholesky), the reduced standard problem, its eigenvalues and (vectors != 0)
+ * eigenvectors, back-transformed -- the LAPACK zhegvd scheme, by rocSOLVER on `stream`.
+ *   H, S [device] n x n column-major, upper triangles read (as flapw_hs_generate writes them with
+ *   the interstitial terms on); on return S holds U in its upper triangle, and with vectors the
+ *   columns of H hold the eigenvectors (S-orthonormal: c^H S c = 1), else H is overwritten.
+ *   w [device] n doubles: the eigenvalues in ascending order.
+ * The call waits for the stream before it returns (it reads the solver's status).
+ * Errors: FLAPW_ERR_ARG, FLAPW_ERR_NOT_POSDEF (S not positive definite, e.g. the muffin-tin S
+ * alone, which has rank <= 2K), FLAPW_ERR_NO_CONVERGENCE, FLAPW_ERR_NOMEM, FLAPW_ERR_DEVICE. */
+flapw_status flapw_eigensolve(flapw_handle h, int n, flapw_z *H, long ldh, flapw_z *S, long lds, double *w,
+                              int vectors, flapw_stream stream);
 
 /* Radial functions and non-spherical radial integrals from radial meshes (section 2.2,
  * eq. simp_Schr; appendix A.2, eq. nonsph_integrals), FP64, Hartree atomic units (the kinetic
@@ -316,7 +382,7 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
  * waits for the recorded events of one kernel family and returns the number of launches and
  * their summed duration in milliseconds since the last flapw_profile_enable(h, 1).
  * Families: "coeffs", "tmat", "qpanel", "repack", "hs_fp64", "slice", "hs_split", "hs_mod",
- * "mod_crt", "leg_prep", "s_legendre", "radial", "graph"
+ * "mod_crt", "leg_prep", "s_legendre", "interstitial", "eigensolve", "radial", "graph"
  * (a whole flapw_plan_launch; kernels inside a graph are not timed one by one).
  * Errors: FLAPW_ERR_ARG for an unknown family or NULL output pointer. */
 flapw_status flapw_profile_enable(flapw_handle h, int on);

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -111,6 +112,40 @@ flapw_status check_potential(flapw_handle h, const flapw_potential *pot, const f
                         if (std::fabs(at(pot->i_du, t, lp, l, L) - at(pot->i_ud, t, l, lp, L)) > tol)
                             return fail(h, FLAPW_ERR_NOT_HERMITIAN, "I^{udot u}(l', l) != I^{u udot}(l, l')");
                     }
+    return FLAPW_OK;
+}
+
+// The interstitial region needs muffin-tin spheres that do not overlap (section 2.2): every pair
+// of atoms (and every atom with its own images) at least R_a + R_b apart over the 27 nearest
+// periodic images.  The lattice (rows a_1, a_2, a_3) must hold the cell volume omega.
+flapw_status check_spheres(flapw_handle h, const flapw_atoms *at, const flapw_radial *rad, const double *lat)
+{
+    if (!lat) return fail(h, FLAPW_ERR_ARG, "NULL lattice");
+    if (!finite_all(lat, 9)) return fail(h, FLAPW_ERR_ARG, "non-finite lattice");
+    const double det = lat[0] * (lat[4] * lat[8] - lat[5] * lat[7]) - lat[1] * (lat[3] * lat[8] - lat[5] * lat[6]) +
+                       lat[2] * (lat[3] * lat[7] - lat[4] * lat[6]);
+    if (!(std::fabs(std::fabs(det) - at->omega) <= 1e-9 * at->omega))
+        return fail(h, FLAPW_ERR_ARG, "|det(lattice)| does not match omega");
+    for (int a = 0; a < at->n_atoms; ++a) {
+        const double ra = rad->rmt[at->type[a]];
+        for (int b = a; b < at->n_atoms; ++b) {
+            const double rb = rad->rmt[at->type[b]];
+            for (int n1 = -1; n1 <= 1; ++n1)
+                for (int n2 = -1; n2 <= 1; ++n2)
+                    for (int n3 = -1; n3 <= 1; ++n3) {
+                        if (a == b && n1 == 0 && n2 == 0 && n3 == 0) continue;
+                        double d2 = 0.0;
+                        for (int c = 0; c < 3; ++c) {
+                            const double d = at->pos[3 * b + c] - at->pos[3 * a + c] + n1 * lat[c] + n2 * lat[3 + c] +
+                                             n3 * lat[6 + c];
+                            d2 += d * d;
+                        }
+                        if (d2 < (ra + rb) * (ra + rb))
+                            return fail(h, FLAPW_ERR_ARG, "muffin-tin spheres of atoms " + std::to_string(a) + " and " +
+                                                              std::to_string(b) + " overlap");
+                    }
+        }
+    }
     return FLAPW_OK;
 }
 
@@ -597,6 +632,8 @@ struct GenPlan {
     int n_k = 0;
     bool split = false;
     bool leg = false;            // S through the addition theorem; the contraction computes H only
+    bool inter = false;          // add the interstitial terms after the muffin-tin parts
+    double v_int = 0.0;
     bool bf16 = false;           // split digits in bf16 (else int8)
     bool mod = false;            // modular split precision (residues mod p_m, CRT)
     ModTable mt{};               // its moduli (mod only)
@@ -681,6 +718,8 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     build_layout(at, rad, true, L, lcut);
     p.n_k = n_k;
     p.leg = leg;
+    p.inter = h->inter;
+    p.v_int = h->v_int;
     p.omega = at->omega;
     p.n_atoms = at->n_atoms;
     p.n_types = rad->n_types;
@@ -780,7 +819,7 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
         p.part = (double *)(p.work + panel_pq);
         p.n_slots = (long long)qpanel_row_tiles(p.ldt) * p.n_atoms;
     }
-    if (p.leg) {
+    if (p.leg || p.inter) {
         const size_t lb = leg_bytes(L, np_max, p.n_types, &p.leg_ab, &p.leg_E);
         if ((e = b.leg->ensure(lb)) != hipSuccess) return dev_fail(h, e, "allocating Legendre scratch");
         p.legbuf = (unsigned char *)b.leg->p;
@@ -789,7 +828,7 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     // contraction descriptors of every batch
     auto &hd = *b.h_desc;
     hd.clear();
-    if (p.leg) {
+    if (p.leg || p.inter) {
         p.o_stiles.resize(n_k);
         p.n_stiles.resize(n_k);
         std::vector<int> tl;
@@ -872,6 +911,30 @@ flapw_status enqueue_s_legendre(flapw_handle h, const GenPlan &p, int i, double2
     return FLAPW_OK;
 }
 
+// Interstitial terms of k-point i added to its H and S; with prep the phases E are formed first
+// (the addition-theorem path has formed them already).
+flapw_status enqueue_interstitial(flapw_handle h, const GenPlan &p, int i, bool prep, hipStream_t s)
+{
+    const Layout &L = p.L;
+    double *khat = (double *)p.legbuf, *ab = (double *)(p.legbuf + p.leg_ab);
+    double2 *E = (double2 *)(p.legbuf + p.leg_E);
+    hipError_t e = hipSuccess;
+    if (prep) {
+        ProfScope prof(h, "leg_prep", s);
+        e = launch_legendre_prep(p.kv.data() + 3 * i, p.ng[i], (int)p.np[i], p.g[i], (const TypeDev *)(p.tables + p.ot),
+                                 p.n_types, (const double *)(p.tables + p.oapos), (const int *)(p.tables + p.olrow),
+                                 p.n_atoms, khat, ab, E, L.ldE, s);
+        if (e != hipSuccess) return dev_fail(h, e, "phase preparation kernel");
+    }
+    ProfScope prof(h, "interstitial", s);
+    e = launch_interstitial(p.g[i], p.kv.data() + 3 * i, E, L.ldE, (const LegTypeRange *)(p.tables + p.olrng),
+                            (const TypeDev *)(p.tables + p.ot), p.n_types, (const int *)(p.desc + p.o_stiles[i]),
+                            p.n_stiles[i], p.ng[i], p.omega, p.v_int, (double2 *)p.S[i], p.ldh[i],
+                            (double2 *)p.H[i], p.ldh[i], s);
+    if (e != hipSuccess) return dev_fail(h, e, "interstitial kernel");
+    return FLAPW_OK;
+}
+
 flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
 {
     flapw_status st = launch_T(h, p.gaunt, p.gp, p.T, p.ldt, s);
@@ -926,9 +989,12 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
                                !p.leg, s);
         }
         if (e != hipSuccess) return dev_fail(h, e, p.split ? "S/H split-precision kernel" : "S/H FP64 kernel");
-        // S (and the L-diagonal part of H beyond the dense block) once H of the batch is written
-        for (int i = bt.i0; p.leg && i < bt.i1; ++i)
-            if ((st = enqueue_s_legendre(h, p, i, (double2 *)p.S[i], p.ldh[i], s)) != FLAPW_OK) return st;
+        // S (and the L-diagonal part of H beyond the dense block) once H of the batch is written,
+        // then the interstitial terms on top of the muffin-tin parts
+        for (int i = bt.i0; i < bt.i1; ++i) {
+            if (p.leg && (st = enqueue_s_legendre(h, p, i, (double2 *)p.S[i], p.ldh[i], s)) != FLAPW_OK) return st;
+            if (p.inter && (st = enqueue_interstitial(h, p, i, !p.leg, s)) != FLAPW_OK) return st;
+        }
     }
     return FLAPW_OK;
 }
@@ -951,6 +1017,7 @@ flapw_status check_generate(flapw_handle h, int n_k, const double *k, const int 
     if (st != FLAPW_OK) return st;
     if ((st = check_atoms(h, at, rad, true)) != FLAPW_OK) return st;
     if ((st = check_potential(h, pot, rad)) != FLAPW_OK) return st;
+    if (h->inter && (st = check_spheres(h, at, rad, h->lattice)) != FLAPW_OK) return st;
     if (h->device < 0) return fail(h, FLAPW_ERR_DEVICE, "no HIP device");
     return FLAPW_OK;
 }
@@ -1013,6 +1080,221 @@ struct TuneScratch {
 };
 
 
+// ------------------------------------------------------------------------ no-allocation scratch
+
+}  // namespace
+
+// Work memory of flapw_hs_contract_noalloc: every device the library runs on holds one copy of this
+// array from the load of the library's code until the process ends.  Host code never uses its name
+// as an address: flapw_create looks up each device's copy with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[(size_t)64 << 20];
+
+namespace {
+
+constexpr size_t kScratchBytes = sizeof(scratch);
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch[kMaxDevices] = {};
+
+// Device address of the scratch array on device `dev`, looked up once with that device current.
+hipError_t record_scratch_address(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev]) return hipSuccess;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = (unsigned char *)p;
+    return hipSuccess;
+}
+
+unsigned char *scratch_address(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[dev];
+}
+
+// ------------------------------------------------------------------ S/H contraction of given A, B, T
+
+// Where the contraction's work buffers come from: the handle's grow-only buffers, or (no_alloc)
+// consecutive 256-byte aligned pieces of the per-device static scratch array.
+struct ContractBufs {
+    flapw_handle h;
+    unsigned char *arena = nullptr;    // device address of this device's scratch array, or NULL
+    size_t used = 0;
+    hipError_t get(DevBuf &b, size_t bytes, void **p)
+    {
+        if (!arena) {
+            hipError_t e = b.ensure(bytes);
+            *p = b.p;
+            return e;
+        }
+        const size_t off = (size_t)round_up((long long)used, 256);
+        if (off + bytes > kScratchBytes) return hipErrorOutOfMemory;     // sized beforehand; never taken
+        used = off + bytes;
+        *p = arena + off;
+        return hipSuccess;
+    }
+    flapw_status upload(DevBuf &b, const std::vector<unsigned char> &src, hipStream_t s, unsigned char **p)
+    {
+        void *d = nullptr;
+        hipError_t e = get(b, src.size(), &d);
+        if (e != hipSuccess) return dev_fail(h, e, arena ? "no-allocation scratch" : "allocating descriptor buffer");
+        e = hipMemcpyAsync(d, src.data(), src.size(), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return dev_fail(h, e, "uploading descriptors");
+        *p = (unsigned char *)d;
+        return FLAPW_OK;
+    }
+};
+
+// Bytes of the scratch the contraction of one problem takes (the pieces ContractBufs::get hands
+// out, each rounded up to 256 bytes).
+size_t contract_scratch_bytes(size_t pq, size_t tables, size_t area, size_t desc)
+{
+    return (size_t)(round_up((long long)pq, 256) + round_up((long long)tables, 256) + round_up((long long)area, 256) +
+                    round_up((long long)desc, 256));
+}
+
+flapw_status hs_contract_impl(flapw_handle h, int n_g, const flapw_atoms *at, const flapw_radial *rad,
+                              const flapw_z *A, const flapw_z *B, long lda, const flapw_z *T, long ldt, flapw_z *H,
+                              flapw_z *S, long ldh, flapw_prec prec, int slices, flapw_stream stream, bool no_alloc)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    if (!A || !B || !T || !H || !S) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
+    if (n_g < 1) return fail(h, FLAPW_ERR_ARG, "n_g must be >= 1");
+    flapw_status st = check_prec(h, prec, slices);
+    if (st != FLAPW_OK) return st;
+    st = check_radial(h, rad);
+    if (st != FLAPW_OK) return st;
+    if ((st = check_atoms(h, at, rad, false)) != FLAPW_OK) return st;
+    Layout L;
+    build_layout(at, rad, true, L);
+    if (lda < L.k) return fail(h, FLAPW_ERR_ARG, "lda < K");
+    if (ldt < 2LL * L.nlmax) return fail(h, FLAPW_ERR_ARG, "ldt < 2 NL_max");
+    if (ldh < n_g) return fail(h, FLAPW_ERR_ARG, "ldh < n_g");
+    hipStream_t s = (hipStream_t)stream;
+    const long long np = round_up(n_g, kTile);
+    // T is taken as given and S from the matrix cores: the key of the default handle settings
+    const int band = effective_band(h, prec, L.kp2, FLAPW_S_GEMM, -1);
+    const int sl = effective_slices(h, prec, L.kp2, FLAPW_S_GEMM, -1, slices);
+    const bool mod = prec == FLAPW_PREC_SPLIT_I8_MOD, split = prec != FLAPW_PREC_FP64;
+    const bool bf16 = prec == FLAPW_PREC_SPLIT_BF16;
+
+    // host side first: row map and atom tables, the tile lists, and the sizes of every buffer
+    // row map of the work layout: >= 0: row of A, <= -2: row -(v+2) of B, -1: zero
+    auto &src = h->host_src;
+    src.assign(L.kp2, -1);
+    long long off = 0;
+    for (int a = 0; a < at->n_atoms; ++a) {
+        const int nl = L.atoms[a].nl;
+        for (int q = 0; q < nl; ++q) {
+            src[L.atom_row[a] + q] = off + q;
+            src[L.atom_row[a] + nl + q] = -(off + q) - 2;
+        }
+        off += nl;
+    }
+    auto &hb = h->host_tables;
+    hb.clear();
+    const size_t osrc = put(hb, src.data(), src.size());
+    const size_t od = put(hb, L.d.data(), L.d.size());
+    const size_t oty = put(hb, L.atom_type.data(), L.atom_type.size());
+    const size_t onl = put(hb, L.atom_nl2.data(), L.atom_nl2.size());
+    const size_t orow = put(hb, L.atom_row.data(), L.atom_row.size());
+    const size_t pq_bytes = (size_t)2 * L.kp2 * np * sizeof(double2);
+    size_t area = 0;
+    long long npm = np;
+    std::vector<TileDev> blocks, tiles;
+    if (mod) {
+        area = (size_t)mod_area_bytes(L.kp2, np, sl);
+        npm = round_up(np, 2 * kModTile);
+        build_mod_tiles({(int)(npm / kModTile)}, 0, 2, blocks, band);
+        build_tiles({(int)(npm / kModTile)}, 0, 2, tiles, band);
+    } else if (split) {
+        area = (size_t)digit_area_bytes(L.kp2, np, sl, digit_bytes(prec));
+        build_tiles({(int)(np / kTile)}, 0, 2, tiles, band);
+    } else {
+        build_tiles({(int)(np / kTile)}, 0, 1, tiles, band);
+    }
+    // descriptors: the problem record (largest of the three kinds) and the tile lists
+    const size_t desc_bytes = 256 + std::max(sizeof(ModProblemDev), std::max(sizeof(SplitProblemDev), sizeof(ProblemDev))) +
+                              256 + blocks.size() * sizeof(TileDev) + 256 + tiles.size() * sizeof(TileDev);
+    ContractBufs bufs{h};
+    if (no_alloc) {
+        const size_t need = contract_scratch_bytes(pq_bytes, hb.size(), area, desc_bytes);
+        if (need > kScratchBytes)
+            return fail(h, FLAPW_ERR_ARG, "problem needs " + std::to_string(need) + " bytes of work memory, above the " +
+                                              std::to_string(kScratchBytes) + "-byte no-allocation scratch");
+    }
+    if (h->device < 0) return fail(h, FLAPW_ERR_DEVICE, "no HIP device");
+    if (no_alloc) {
+        bufs.arena = scratch_address(h->device);
+        if (!bufs.arena) return fail(h, FLAPW_ERR_DEVICE, "no-allocation scratch address unknown for this device");
+    }
+
+    void *pq = nullptr;
+    hipError_t e = bufs.get(h->work, pq_bytes, &pq);
+    if (e != hipSuccess) return dev_fail(h, e, "allocating work buffer");
+    double2 *P = (double2 *)pq;
+    double2 *Q = P + L.kp2 * np;
+    unsigned char *base = nullptr;
+    if ((st = bufs.upload(h->tables, hb, s, &base)) != FLAPW_OK) return st;
+    void *ar = nullptr;
+    if (split && (e = bufs.get(h->digits, area, &ar)) != hipSuccess)
+        return dev_fail(h, e, mod ? "allocating residue buffer" : "allocating digit buffer");
+    {
+        ProfScope prof(h, "repack", s);
+        e = launch_repack((const double2 *)A, (const double2 *)B, lda, n_g, nullptr, 0, (const long long *)(base + osrc), P,
+                          L.kp2, (int)L.kp2, (int)np, s);
+    }
+    if (e != hipSuccess) return dev_fail(h, e, "repack kernel");
+    {
+        ProfScope prof(h, "qpanel", s);
+        e = launch_qpanel((const double2 *)T, ldt, ldt * ldt, (const int *)(base + oty), (const int *)(base + onl),
+                          (const long long *)(base + orow), at->n_atoms, P, Q, L.kp2, (int)np, L.kp2, false, 0,
+                          nullptr, nullptr, s);
+    }
+    if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
+    ProblemDev pd{P, Q, (const double *)(base + od), (double2 *)H, (double2 *)S, L.kp2, ldh, n_g, (int)L.kp2};
+    auto &hs = h->host_sdesc;
+    hs.clear();
+    unsigned char *db = nullptr;
+    if (!split) {
+        const size_t op = put(hs, &pd, 1);
+        const size_t ot = put(hs, tiles.data(), tiles.size());
+        if ((st = bufs.upload(h->tiles, hs, s, &db)) != FLAPW_OK) return st;
+        ProfScope prof(h, "hs_fp64", s);
+        e = launch_hs_fp64((const ProblemDev *)(db + op), (const TileDev *)(db + ot), (int)tiles.size(), true, s);
+        if (e != hipSuccess) return dev_fail(h, e, "S/H FP64 kernel");
+        return FLAPW_OK;
+    }
+    if (mod) {
+        const ModArea ma = mod_area(ar, L.kp2, np, sl);
+        const ModTable mt = make_mod_table(sl);
+        if ((st = mod_slice_problem(h, pd, np, ma, mt, true, nullptr, 0, s)) != FLAPW_OK) return st;
+        const ModProblemDev mp = mod_problem(ma, (double2 *)H, (double2 *)S, ldh, n_g, L.kp2);
+        const size_t op = put(hs, &mp, 1);
+        const size_t ob = put(hs, blocks.data(), blocks.size());
+        const size_t ot = put(hs, tiles.data(), tiles.size());
+        if ((st = bufs.upload(h->sdesc, hs, s, &db)) != FLAPW_OK) return st;
+        e = launch_mod_pair(h, (const ModProblemDev *)(db + op), (const TileDev *)(db + ob), (int)blocks.size(),
+                            (const TileDev *)(db + ot), (int)tiles.size(), mt, s);
+        if (e != hipSuccess) return dev_fail(h, e, "S/H modular split kernels");
+        return FLAPW_OK;
+    }
+    const DigitArea da = digit_area(ar, L.kp2, np, sl, digit_bytes(prec));
+    if ((st = slice_problem(h, pd, np, sl, da, bf16, s)) != FLAPW_OK) return st;
+    SplitProblemDev sp{da.L, da.RS, da.RH, da.eL, da.eRS, da.eRH, (double2 *)H, (double2 *)S, ldh, n_g, (int)L.kp2};
+    const size_t op = put(hs, &sp, 1);
+    const size_t ot = put(hs, tiles.data(), tiles.size());
+    if ((st = bufs.upload(h->sdesc, hs, s, &db)) != FLAPW_OK) return st;
+    ProfScope prof(h, "hs_split", s);
+    e = launch_split_any(bf16, (const SplitProblemDev *)(db + op), (const TileDev *)(db + ot), (int)tiles.size(), sl, s);
+    if (e != hipSuccess) return dev_fail(h, e, "S/H split-precision kernel");
+    return FLAPW_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------ C-ABI
@@ -1032,6 +1314,14 @@ flapw_status flapw_create(flapw_handle *h)
         (void)hipGetLastError();
         c->device = -1;
         c->err = "no HIP device";
+    } else {
+        // the no-allocation scratch of this device; on failure only flapw_hs_contract_noalloc
+        // is unavailable (it then returns FLAPW_ERR_DEVICE)
+        hipError_t e = record_scratch_address(c->device);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            c->err = std::string("no-allocation scratch: ") + hipGetErrorString(e);
+        }
     }
     *h = c;
     return FLAPW_OK;
@@ -1054,6 +1344,7 @@ flapw_status flapw_destroy(flapw_handle h)
     h->leg.release();
     h->radial.release();
     split_release(h);
+    eigen_release(h);
     delete h;
     return FLAPW_OK;
 }
@@ -1068,6 +1359,8 @@ const char *flapw_status_string(flapw_status s)
         case FLAPW_ERR_NOMEM: return "out of device memory";
         case FLAPW_ERR_DEVICE: return "HIP device error";
         case FLAPW_ERR_UNSUPPORTED: return "unsupported request";
+        case FLAPW_ERR_NOT_POSDEF: return "S is not positive definite";
+        case FLAPW_ERR_NO_CONVERGENCE: return "eigensolver did not converge";
     }
     return "unknown status";
 }
@@ -1088,6 +1381,13 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
     for (int i = 0; digit_err && i < 4; ++i) digit_err[i] = std::nan("");
     for (int i = 0; band_ms && i < 5; ++i) band_ms[i] = std::nan("");
     const bool split = prec != FLAPW_PREC_FP64;
+    // the gate and the timing cover the muffin-tin parts (the interstitial terms are FP64 either way)
+    struct InterOff {
+        flapw_handle h;
+        bool was;
+        ~InterOff() { h->inter = was; }
+    } inter_off{h, h->inter};
+    h->inter = false;
     TuneScratch scratch;
     hipError_t e;
     int chosen = 0;
@@ -1185,8 +1485,9 @@ flapw_status flapw_profile_query(flapw_handle h, const char *family, int *launch
 {
     if (!h) return FLAPW_ERR_ARG;
     if (!family || !launches || !total_ms) return fail(h, FLAPW_ERR_ARG, "NULL argument");
-    static const char *known[] = {"coeffs",   "tmat",  "qpanel",   "repack",     "hs_fp64", "slice",
-                                  "hs_split", "hs_mod", "mod_crt", "graph", "leg_prep", "s_legendre", "radial"};
+    static const char *known[] = {"coeffs",   "tmat",      "qpanel",   "repack",     "hs_fp64",
+                                  "slice",    "hs_split",  "hs_mod",   "mod_crt",    "graph",
+                                  "leg_prep", "s_legendre", "interstitial", "eigensolve", "radial"};
     bool ok = false;
     for (const char *k : known) ok = ok || std::strcmp(k, family) == 0;
     if (!ok) return fail(h, FLAPW_ERR_ARG, std::string("unknown kernel family ") + family);
@@ -1219,6 +1520,7 @@ flapw_status flapw_release_workspace(flapw_handle h)
     h->leg.release();
     h->radial.release();
     split_release(h);
+    h->eig.release();
     return FLAPW_OK;
 }
 
@@ -1276,97 +1578,18 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
                                const flapw_z *A, const flapw_z *B, long lda, const flapw_z *T, long ldt, flapw_z *H,
                                flapw_z *S, long ldh, flapw_prec prec, int slices, flapw_stream stream)
 {
-    if (!h) return FLAPW_ERR_ARG;
-    if (!A || !B || !T || !H || !S) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
-    if (n_g < 1) return fail(h, FLAPW_ERR_ARG, "n_g must be >= 1");
-    flapw_status st = check_prec(h, prec, slices);
-    if (st != FLAPW_OK) return st;
-    st = check_radial(h, rad);
-    if (st != FLAPW_OK) return st;
-    if ((st = check_atoms(h, at, rad, false)) != FLAPW_OK) return st;
-    Layout L;
-    build_layout(at, rad, true, L);
-    if (lda < L.k) return fail(h, FLAPW_ERR_ARG, "lda < K");
-    if (ldt < 2LL * L.nlmax) return fail(h, FLAPW_ERR_ARG, "ldt < 2 NL_max");
-    if (ldh < n_g) return fail(h, FLAPW_ERR_ARG, "ldh < n_g");
-    if (h->device < 0) return fail(h, FLAPW_ERR_DEVICE, "no HIP device");
-    hipStream_t s = (hipStream_t)stream;
-    const long long np = round_up(n_g, kTile);
-    hipError_t e = h->work.ensure((size_t)2 * L.kp2 * np * sizeof(double2));
-    if (e != hipSuccess) return dev_fail(h, e, "allocating work buffer");
-    double2 *P = (double2 *)h->work.p;
-    double2 *Q = P + L.kp2 * np;
-    // row map of the work layout: >= 0: row of A, <= -2: row -(v+2) of B, -1: zero
-    auto &src = h->host_src;
-    src.assign(L.kp2, -1);
-    long long off = 0;
-    for (int a = 0; a < at->n_atoms; ++a) {
-        const int nl = L.atoms[a].nl;
-        for (int q = 0; q < nl; ++q) {
-            src[L.atom_row[a] + q] = off + q;
-            src[L.atom_row[a] + nl + q] = -(off + q) - 2;
-        }
-        off += nl;
-    }
-    auto &hb = h->host_tables;
-    hb.clear();
-    const size_t osrc = put(hb, src.data(), src.size());
-    const size_t od = put(hb, L.d.data(), L.d.size());
-    const size_t oty = put(hb, L.atom_type.data(), L.atom_type.size());
-    const size_t onl = put(hb, L.atom_nl2.data(), L.atom_nl2.size());
-    const size_t orow = put(hb, L.atom_row.data(), L.atom_row.size());
-    if ((st = upload(h, h->tables, hb, s)) != FLAPW_OK) return st;
-    unsigned char *base = (unsigned char *)h->tables.p;
-    {
-        ProfScope prof(h, "repack", s);
-        e = launch_repack((const double2 *)A, (const double2 *)B, lda, n_g, nullptr, 0, (const long long *)(base + osrc), P,
-                      L.kp2, (int)L.kp2, (int)np, s);
-    }
-    if (e != hipSuccess) return dev_fail(h, e, "repack kernel");
-    {
-        ProfScope prof(h, "qpanel", s);
-        e = launch_qpanel((const double2 *)T, ldt, ldt * ldt, (const int *)(base + oty), (const int *)(base + onl),
-                          (const long long *)(base + orow), at->n_atoms, P, Q, L.kp2, (int)np, L.kp2, false, 0,
-                          nullptr, nullptr, s);
-    }
-    if (e != hipSuccess) return dev_fail(h, e, "Q panel kernel");
-    ProblemDev pd{P, Q, (const double *)(base + od), (double2 *)H, (double2 *)S, L.kp2, ldh, n_g, (int)L.kp2};
-    std::vector<int> npt{(int)(np / kTile)};
-    // T is taken as given and S from the matrix cores: the key of the default handle settings
-    const int band = effective_band(h, prec, L.kp2, FLAPW_S_GEMM, -1);
-    if (prec == FLAPW_PREC_FP64) return run_fp64(h, {pd}, npt, band, s);
-    const int sl = effective_slices(h, prec, L.kp2, FLAPW_S_GEMM, -1, slices);
-    if (prec == FLAPW_PREC_SPLIT_I8_MOD) {
-        e = h->digits.ensure((size_t)mod_area_bytes(L.kp2, np, sl));
-        if (e != hipSuccess) return dev_fail(h, e, "allocating residue buffer");
-        const ModArea ma = mod_area(h->digits.p, L.kp2, np, sl);
-        const ModTable mt = make_mod_table(sl);
-        if ((st = mod_slice_problem(h, pd, np, ma, mt, true, nullptr, 0, s)) != FLAPW_OK) return st;
-        std::vector<TileDev> blocks, tiles;
-        build_mod_tiles({(int)(ma.npm / kModTile)}, 0, 2, blocks, band);
-        build_tiles({(int)(ma.npm / kModTile)}, 0, 2, tiles, band);
-        const ModProblemDev mp = mod_problem(ma, (double2 *)H, (double2 *)S, ldh, n_g, L.kp2);
-        auto &hs = h->host_sdesc;
-        hs.clear();
-        const size_t op = put(hs, &mp, 1);
-        const size_t ob = put(hs, blocks.data(), blocks.size());
-        const size_t ot = put(hs, tiles.data(), tiles.size());
-        if ((st = upload(h, h->sdesc, hs, s)) != FLAPW_OK) return st;
-        unsigned char *db = (unsigned char *)h->sdesc.p;
-        e = launch_mod_pair(h, (const ModProblemDev *)(db + op), (const TileDev *)(db + ob), (int)blocks.size(),
-                            (const TileDev *)(db + ot), (int)tiles.size(), mt, s);
-        if (e != hipSuccess) return dev_fail(h, e, "S/H modular split kernels");
-        return FLAPW_OK;
-    }
-    const int eb = digit_bytes(prec);
-    e = h->digits.ensure((size_t)digit_area_bytes(L.kp2, np, sl, eb));
-    if (e != hipSuccess) return dev_fail(h, e, "allocating digit buffer");
-    const DigitArea da = digit_area(h->digits.p, L.kp2, np, sl, eb);
-    const bool bf16 = prec == FLAPW_PREC_SPLIT_BF16;
-    if ((st = slice_problem(h, pd, np, sl, da, bf16, s)) != FLAPW_OK) return st;
-    SplitProblemDev sp{da.L, da.RS, da.RH, da.eL, da.eRS, da.eRH, (double2 *)H, (double2 *)S, ldh, n_g, (int)L.kp2};
-    return run_split(h, {sp}, npt, sl, band, bf16, s);
+    return hs_contract_impl(h, n_g, at, rad, A, B, lda, T, ldt, H, S, ldh, prec, slices, stream, false);
 }
+
+flapw_status flapw_hs_contract_noalloc(flapw_handle h, int n_g, const flapw_atoms *at, const flapw_radial *rad,
+                                       const flapw_z *A, const flapw_z *B, long lda, const flapw_z *T, long ldt,
+                                       flapw_z *H, flapw_z *S, long ldh, flapw_prec prec, int slices,
+                                       flapw_stream stream)
+{
+    return hs_contract_impl(h, n_g, at, rad, A, B, lda, T, ldt, H, S, ldh, prec, slices, stream, true);
+}
+
+long long flapw_noalloc_scratch_bytes(void) { return (long long)kScratchBytes; }
 
 flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const int *n_g, const double *const *g,
                                const flapw_atoms *at, const flapw_radial *rad, const flapw_potential *pot,
@@ -1448,6 +1671,70 @@ flapw_status flapw_s_legendre(flapw_handle h, const double *k, int n_g, const do
     if (e != hipSuccess) return dev_fail(h, e, "allocating Legendre scratch");
     p.legbuf = (unsigned char *)h->leg.p;
     return enqueue_s_legendre(h, p, 0, (double2 *)S, lds, s);
+}
+
+flapw_status flapw_interstitial(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
+                                const flapw_radial *rad, const double *lattice, double v_int, flapw_z *H,
+                                flapw_z *S, long ldh, flapw_stream stream)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    if (!k || !g || !S || !H) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
+    if (n_g < 1) return fail(h, FLAPW_ERR_ARG, "n_g must be >= 1");
+    if (ldh < n_g) return fail(h, FLAPW_ERR_ARG, "ldh < n_g");
+    if (!finite_all(k, 3) || !std::isfinite(v_int)) return fail(h, FLAPW_ERR_ARG, "non-finite k or v_int");
+    flapw_status st = check_radial(h, rad);
+    if (st != FLAPW_OK) return st;
+    if ((st = check_atoms(h, at, rad, true)) != FLAPW_OK) return st;
+    if ((st = check_spheres(h, at, rad, lattice)) != FLAPW_OK) return st;
+    if (h->device < 0) return fail(h, FLAPW_ERR_DEVICE, "no HIP device");
+    hipStream_t s = (hipStream_t)stream;
+    GenPlan p;
+    Layout &L = p.L;
+    build_layout(at, rad, true, L);
+    p.inter = true;
+    p.v_int = v_int;
+    p.omega = at->omega;
+    p.n_atoms = at->n_atoms;
+    p.n_types = rad->n_types;
+    p.kv.assign(k, k + 3);
+    p.g.assign(1, g);
+    p.ng.assign(1, n_g);
+    p.np.assign(1, round_up(n_g, kTile));
+    p.S.assign(1, S);
+    p.H.assign(1, H);
+    p.ldh.assign(1, ldh);
+    auto &ht = h->host_tables;
+    ht.clear();
+    p.ot = put(ht, L.types.data(), L.types.size());
+    p.oapos = put(ht, L.apos.data(), L.apos.size());
+    p.olrow = put(ht, L.leg_row.data(), L.leg_row.size());
+    p.olrng = put(ht, L.leg_ranges.data(), L.leg_ranges.size());
+    if ((st = upload(h, h->tables, ht, s)) != FLAPW_OK) return st;
+    p.tables = (unsigned char *)h->tables.p;
+    std::vector<int> tl;
+    s_tiles(p.np[0], tl);
+    auto &hd = h->host_tiles;
+    hd.clear();
+    p.o_stiles.assign(1, put(hd, tl.data(), tl.size()));
+    p.n_stiles.assign(1, (int)tl.size() / 2);
+    if ((st = upload(h, h->tiles, hd, s)) != FLAPW_OK) return st;
+    p.desc = (unsigned char *)h->tiles.p;
+    hipError_t e = h->leg.ensure(leg_bytes(L, p.np[0], p.n_types, &p.leg_ab, &p.leg_E));
+    if (e != hipSuccess) return dev_fail(h, e, "allocating phase scratch");
+    p.legbuf = (unsigned char *)h->leg.p;
+    return enqueue_interstitial(h, p, 0, true, s);
+}
+
+flapw_status flapw_set_interstitial(flapw_handle h, int on, const double *lattice, double v_int)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    if (on && !lattice) return fail(h, FLAPW_ERR_ARG, "NULL lattice");
+    if (!std::isfinite(v_int)) return fail(h, FLAPW_ERR_ARG, "non-finite v_int");
+    if (on && !finite_all(lattice, 9)) return fail(h, FLAPW_ERR_ARG, "non-finite lattice");
+    h->inter = on != 0;
+    h->v_int = v_int;
+    if (on) std::memcpy(h->lattice, lattice, sizeof(h->lattice));
+    return FLAPW_OK;
 }
 
 namespace {
@@ -1584,6 +1871,7 @@ flapw_status flapw_plan_create(flapw_handle h, int n_k, const double *k, const i
     if (e == hipSuccess && prec == FLAPW_PREC_SPLIT_BF16) e = init_split_bf16_kernels();
     if (e == hipSuccess && prec == FLAPW_PREC_SPLIT_I8_MOD) e = init_mod_kernels();
     if (e == hipSuccess && h->s_method == FLAPW_S_LEGENDRE) e = init_legendre_kernels();
+    if (e == hipSuccess && h->inter) e = init_interstitial_kernel();
     if (e != hipSuccess) return dev_fail(h, e, "kernel attributes");
     flapw_plan_s *pl = new (std::nothrow) flapw_plan_s();
     if (!pl) return fail(h, FLAPW_ERR_NOMEM, "plan allocation");

@@ -153,6 +153,14 @@ hipError_t launch_s_legendre(const double *khat, const double *ab, const double2
                              double scale, double2 *S, long long lds, const double *ud_norm2, const double *hsph,
                              int lh0, double2 *H, long long ldh, hipStream_t s);
 
+// Interstitial S and H (interstitial.hip): phases E and ranges as for launch_s_legendre; g the
+// n x 3 Cartesian G list; adds to the upper triangles of S and H.
+hipError_t init_interstitial_kernel();
+hipError_t launch_interstitial(const double *g, const double kvec[3], const double2 *E, long long ldE,
+                               const LegTypeRange *ranges, const TypeDev *types, int n_types, const int *tiles,
+                               int n_tiles, int n, double omega, double v_int, double2 *S, long long lds, double2 *H,
+                               long long ldh, hipStream_t s);
+
 // Modular split precision (split_mod.hip).  Moduli p_m, 1/p_m as double-double, the CRT
 // constants w_m = (M/p_m)^-1 mod p_m, M = prod p_m as double-double, and the integer bits B.
 constexpr int kModCap = 14;

@@ -63,6 +63,11 @@ struct flapw_context {
     flapw::DevBuf radial;      // radial setup: meshes, potentials, functions and integral tables
     int s_method = 0;          // flapw_s_method of flapw_hs_generate and flapw_plan_create
     int lnonsph = -1;          // structured T (flapw_set_lnonsph); -1: dense T
+    bool inter = false;        // flapw_set_interstitial: generation adds the interstitial terms
+    double v_int = 0.0;
+    double lattice[9] = {};
+    void *blas = nullptr;      // rocblas_handle of flapw_eigensolve (created on first use)
+    flapw::DevBuf eig;         // flapw_eigensolve: off-diagonal workspace and status word
     std::vector<unsigned char> host_tables, host_gaunt, host_tiles, host_sdesc;
     std::vector<long long> host_src;
     // tuning (flapw_tune): chosen digit count and tile band per (precision, padded contraction rows,
@@ -158,6 +163,8 @@ struct ProfScope {
 
 // split precision (split.hip)
 void split_release(flapw_handle h);
+// the eigensolver's rocBLAS handle and workspace (eigen.cpp)
+void eigen_release(flapw_handle h);
 long long split_bytes(flapw_handle h);
 
 }  // namespace flapw

@@ -31,14 +31,16 @@ PRECISIONS = {"fp64": FP64, "bf16": SPLIT_BF16, "fp32": SPLIT_FP32, "i8": SPLIT_
 S_METHODS = {"gemm": 0, "legendre": 1}
 
 _STATUS = {0: "FLAPW_OK", -1: "FLAPW_ERR_ARG", -2: "FLAPW_ERR_WRONSKIAN", -3: "FLAPW_ERR_NOT_HERMITIAN",
-           -4: "FLAPW_ERR_NOMEM", -5: "FLAPW_ERR_DEVICE", -6: "FLAPW_ERR_UNSUPPORTED"}
+           -4: "FLAPW_ERR_NOMEM", -5: "FLAPW_ERR_DEVICE", -6: "FLAPW_ERR_UNSUPPORTED", -7: "FLAPW_ERR_NOT_POSDEF",
+           -8: "FLAPW_ERR_NO_CONVERGENCE"}
 
 EXPORTS = ["flapw_create", "flapw_destroy", "flapw_status_string", "flapw_last_error", "flapw_workspace_bytes",
            "flapw_release_workspace",
            "flapw_coeffs", "flapw_build_T", "flapw_hs_contract", "flapw_hs_generate", "flapw_set_s_method",
            "flapw_set_lnonsph", "flapw_s_legendre", "flapw_plan_create",
            "flapw_plan_launch", "flapw_plan_destroy", "flapw_tune", "flapw_profile_enable", "flapw_profile_query",
-           "flapw_radial_setup"]
+           "flapw_radial_setup", "flapw_hs_contract_noalloc", "flapw_noalloc_scratch_bytes", "flapw_interstitial",
+           "flapw_set_interstitial", "flapw_eigensolve"]
 
 
 class FlapwError(RuntimeError):
@@ -95,6 +97,9 @@ def load_library(path: str = LIB_PATH):
         lib.flapw_coeffs.argtypes = [P, P, I, P, P, P, P, P, L, P]
         lib.flapw_build_T.argtypes = [P, P, P, P, L, P]
         lib.flapw_hs_contract.argtypes = [P, I, P, P, P, P, L, P, L, P, P, L, I, I, P]
+        lib.flapw_hs_contract_noalloc.argtypes = [P, I, P, P, P, P, L, P, L, P, P, L, I, I, P]
+        lib.flapw_noalloc_scratch_bytes.argtypes = []
+        lib.flapw_noalloc_scratch_bytes.restype = ctypes.c_longlong
         lib.flapw_hs_generate.argtypes = [P, I, P, P, P, P, P, P, P, P, P, I, I, P]
         lib.flapw_set_s_method.argtypes = [P, I]
         lib.flapw_set_lnonsph.argtypes = [P, I]
@@ -107,6 +112,9 @@ def load_library(path: str = LIB_PATH):
         lib.flapw_profile_enable.argtypes = [P, I]
         lib.flapw_profile_query.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_double)]
         lib.flapw_radial_setup.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
+        lib.flapw_interstitial.argtypes = [P, P, I, P, P, P, P, ctypes.c_double, P, P, L, P]
+        lib.flapw_set_interstitial.argtypes = [P, I, P, ctypes.c_double]
+        lib.flapw_eigensolve.argtypes = [P, I, P, L, P, L, P, I, P]
         for f in EXPORTS:
             getattr(lib, f).restype = getattr(lib, f).restype or ctypes.c_int
         _lib = lib
@@ -243,7 +251,11 @@ class Flapw:
                                             _stream(stream)))
         return T
 
-    def hs_contract(self, system, A, B, T, prec="fp64", slices: int = 0, H=None, S=None, stream=None):
+    def hs_contract(self, system, A, B, T, prec="fp64", slices: int = 0, H=None, S=None, stream=None,
+                    no_alloc: bool = False):
+        """S and H from given A, B (tensors (n_g, ld)) and T.  no_alloc: flapw_hs_contract_noalloc (work
+        buffers in the library's static per-device scratch; the outputs, when not given, are still
+        allocated here by torch)."""
         import torch
         self._keep = []
         n_g = int(A.shape[0])
@@ -252,7 +264,8 @@ class Flapw:
         if S is None:
             S = torch.zeros((n_g, n_g), dtype=torch.complex128, device=A.device)
         rad, at = self._radial(system), self._atoms(system)
-        self._check(self._lib.flapw_hs_contract(self._h, n_g, ctypes.byref(at), ctypes.byref(rad), _dptr(A), _dptr(B),
+        fn = self._lib.flapw_hs_contract_noalloc if no_alloc else self._lib.flapw_hs_contract
+        self._check(fn(self._h, n_g, ctypes.byref(at), ctypes.byref(rad), _dptr(A), _dptr(B),
                                                 int(A.shape[1]), _dptr(T), int(T.shape[-1]), _dptr(H), _dptr(S),
                                                 int(H.shape[1]), PRECISIONS.get(prec, prec), int(slices),
                                                 _stream(stream)))
@@ -266,6 +279,36 @@ class Flapw:
     def set_lnonsph(self, lnonsph: int = -1):
         """Structured T: non-spherical terms only for l', l <= lnonsph (-1: dense T)."""
         self._check(self._lib.flapw_set_lnonsph(self._h, int(lnonsph)))
+
+    def interstitial(self, system, k, g, H, S, v_int: float = 0.0, stream=None):
+        """Adds the interstitial S and H of one k-point to the upper triangles of H and S (tensors
+        (n_g, ld)); g: device tensor (n_g, 3).  system needs `lattice` (3 x 3 rows)."""
+        self._keep = []
+        kk, lat = _f64(k), _f64(system.lattice)
+        rad, at = self._radial(system), self._atoms(system)
+        self._keep += [kk, lat]
+        self._check(self._lib.flapw_interstitial(self._h, _ptr(kk), int(g.shape[0]), _dptr(g), ctypes.byref(at),
+                                                 ctypes.byref(rad), _ptr(lat), float(v_int), _dptr(H), _dptr(S),
+                                                 int(H.shape[1]), _stream(stream)))
+        return H, S
+
+    def set_interstitial(self, on: bool = True, lattice=None, v_int: float = 0.0):
+        """Generation (hs_generate, plan) adds the interstitial terms, giving the full H and S."""
+        lat = _f64(lattice) if lattice is not None else None
+        self._check(self._lib.flapw_set_interstitial(self._h, int(bool(on)), None if lat is None else _ptr(lat),
+                                                     float(v_int)))
+
+    def eigensolve(self, H, S, vectors: bool = True, w=None, stream=None):
+        """H c = eps S c in place (rocSOLVER zhegvd on the upper triangles): returns (w, H) with the
+        eigenvalues ascending and, with vectors, the S-orthonormal eigenvectors in the columns of the
+        column-major H (tensor row t = column t); S then holds its Cholesky factor."""
+        import torch
+        n = int(H.shape[0])
+        if w is None:
+            w = torch.empty(n, dtype=torch.float64, device=H.device)
+        self._check(self._lib.flapw_eigensolve(self._h, n, _dptr(H), int(H.shape[1]), _dptr(S), int(S.shape[1]),
+                                               _dptr(w), int(bool(vectors)), _stream(stream)))
+        return w, H
 
     def radial_setup(self, n_r: int, r0, rmt, v_sph, e_l, lmax, v_lm, lpot: int, stream=None):
         """Radial boundary data and the four non-spherical integral tables from radial meshes

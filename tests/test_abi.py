@@ -39,7 +39,7 @@ def test_header_symbols_exported(lib):
 
 
 def test_status_strings(lib):
-    for s in (0, -1, -2, -3, -4, -5, -6):
+    for s in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert lib.flapw_status_string(s)
     assert lib.flapw_status_string(-2) == b"vanishing Wronskian"
 
@@ -325,3 +325,58 @@ def test_release_workspace(handle, lib):
     assert handle.workspace_bytes == 0
     handle.release_workspace()
     assert lib.flapw_release_workspace(None) == -1
+
+
+def test_interstitial_validation(handle, lib):
+    """flapw_interstitial and flapw_set_interstitial reject overlapping spheres, a lattice that does
+    not hold omega, NULL pointers and bad sizes before touching the device."""
+    from paper_1602_06589_amd import flapw as F
+    import torch
+    P = ctypes.c_void_p
+    k = np.zeros(3)
+
+    def call(cell, lat=None, n=None, ldh=None, v=0.0):
+        handle._keep = []
+        rad, at = handle._radial(cell), handle._atoms(cell)
+        la = F._f64(cell.lattice if lat is None else lat)
+        handle._keep += [la]
+        nn = cell.n_g(0) if n is None else n
+        return lib.flapw_interstitial(handle._h, F._ptr(k), nn, P(0x1000), ctypes.byref(at), ctypes.byref(rad),
+                                      F._ptr(la), v, P(0x2000), P(0x3000), nn if ldh is None else ldh, None)
+
+    over = synthcells.config(0)                                      # two spheres 0.8 bohr apart
+    assert synthcells.min_sphere_gap(over) < 0
+    assert call(over) == -1
+    assert b"overlap" in lib.flapw_last_error(handle._h)
+    sep = synthcells.config_separated(0)
+    assert call(sep, lat=sep.lattice * 1.01) == -1                   # |det| != omega
+    assert call(sep, n=0) == -1
+    assert call(sep, ldh=10) == -1
+    assert call(sep, v=float("nan")) == -1
+    # a sphere overlapping its own periodic image
+    big = synthcells.custom_cell("img", 3.0, np.array([[1.0, 1.0, 1.0]]), np.zeros(1, np.int32), [2], [1.6], 2, 20,
+                                 [3])
+    assert call(big) == -1
+    if not torch.cuda.is_available():
+        assert call(sep) == -5
+    assert lib.flapw_set_interstitial(handle._h, 1, None, 0.0) == -1
+    assert lib.flapw_set_interstitial(handle._h, 0, None, float("inf")) == -1
+    la = F._f64(over.lattice)
+    assert lib.flapw_set_interstitial(handle._h, 1, F._ptr(la), 0.0) == 0
+    # with the setting on, generation validates the spheres too
+    assert lib.flapw_hs_generate(*_gen_args(handle, over), 0, 0, None) == -1
+    assert b"overlap" in lib.flapw_last_error(handle._h)
+    assert lib.flapw_set_interstitial(handle._h, 0, None, 0.0) == 0
+
+
+def test_eigensolve_validation(handle, lib):
+    import torch
+    P = ctypes.c_void_p
+    assert lib.flapw_eigensolve(handle._h, 0, P(0x1000), 1, P(0x2000), 1, P(0x3000), 1, None) == -1
+    assert lib.flapw_eigensolve(handle._h, 10, P(0x1000), 9, P(0x2000), 10, P(0x3000), 1, None) == -1
+    assert lib.flapw_eigensolve(handle._h, 10, None, 10, P(0x2000), 10, P(0x3000), 1, None) == -1
+    assert lib.flapw_eigensolve(handle._h, 10, P(0x1000), 10, P(0x2000), 10, None, 1, None) == -1
+    if not torch.cuda.is_available():
+        assert lib.flapw_eigensolve(handle._h, 10, P(0x1000), 10, P(0x2000), 10, P(0x3000), 1, None) == -5
+    for s in (-7, -8):
+        assert lib.flapw_status_string(s) != b"unknown status"

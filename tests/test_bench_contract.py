@@ -44,16 +44,17 @@ def test_traffic_line_is_read_for_the_current_source(tmp_path, monkeypatch):
     sha = bench.kernel_sources_sha("i8mod")
     p = tmp_path / "traffic.txt"
     p.write_text("notes\n"
-                 f"traffic kernel=hs_mod workload=c4_scale src_sha={sha} bytes_per_launch=123000\n"
+                 f"traffic kernel=hs_mod workload=c4_scale src_sha={sha} slices=11 bytes_per_launch=123000\n"
                  "traffic kernel=hs_mod workload=c1_realistic src_sha=0000000000000000 bytes_per_launch=7\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
-    assert bench.read_traffic("i8mod", "c4_scale") == 123000.0
+    assert bench.read_traffic("i8mod", "c4_scale", 11) == 123000.0
+    assert bench.read_traffic("i8mod", "c4_scale", 10) is None           # counters of another modulus count
     # a line recorded for another source version is ignored
     assert bench.read_traffic("i8mod", "c1_realistic") is None
     # other kernels and workloads without a line
     assert bench.read_traffic("fp64", "c4_scale") is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
-    assert bench.read_traffic("i8mod", "c4_scale") is None
+    assert bench.read_traffic("i8mod", "c4_scale", 11) is None
 
 
 @pytest.mark.parametrize("prec,slices,factor", [("i8mod", 10, 10.0), ("i8mod", 11, 11.0), ("i8", 6, 21.0),
