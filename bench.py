@@ -10,9 +10,9 @@ A path is a precision (i8mod, i8, bf16 or fp64 for the S/H contraction) with an 
 then comes from the addition theorem (section 3.1) and the contraction computes H alone.  The
 first path is the headline; the default pair is the modular int8 split and the FP64 comparator.
 Before its timing, each split path runs the library's autotuner on k-point 0 (flapw_tune: the
-smallest modulus or digit count whose H and S errors, extrapolated from a sampled block to the
-whole matrix, are at most 1e-10 / 2, then the fastest tile band); --slices fixes the count
-instead and --no-tune takes the defaults.
+smallest modulus or digit count whose H and S errors, estimated for the whole matrix from a random
+sample of basis functions, are at most 2/3 of 1e-10, then the fastest tile band and stage depth);
+--slices fixes the count instead and --no-tune takes the defaults.
 A step is one generation over every k-point of the workload (the whole path), replayed from a
 HIP graph (flapw_plan_launch; --eager: flapw_hs_generate calls).  The headline takes W untimed
 and K timed steps; every other path at most 1 and 3 (a wall-clock guard trims them further and
@@ -57,7 +57,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
 
 def kernel_sources_sha(prec: str) -> str:
     names = {"fp64": ["contract_fp64.hip"], "i8": ["split.hip"], "bf16": ["split_bf16.hip"],
-             "i8mod": ["split_mod.hip"]}[prec]
+             "i8mod": ["mod_contract.hip"]}[prec]
     h = hashlib.sha256()
     for n in names:
         with open(os.path.join(ROOT, "paper_1602_06589_amd", "csrc", n), "rb") as f:
@@ -222,6 +222,52 @@ def step_plan(is_head: bool, steps: int, warmup: int):
     return min(warmup, 1), min(steps, 3), 1
 
 
+def operand_study(config: int, slices: int, reps: int = 2):
+    """The modular contraction of one k-point-sized problem (the workload's atoms and K, its first
+    k-point's N) through flapw_hs_contract on two operand sets of the same shape: seeded random
+    complex A, B (residues spread over every int8 value) and constant A = B = 1 + i.  T is the
+    identity and every ||udot||^2 is 1, so that P, d.P and Q are the same matrix and, in the constant
+    case, every residue of a modulus is the same byte.  The instruction stream is identical; only the
+    switching activity of the matrix-core operands differs, so a time difference shows a
+    power-limited clock.  Returns the contraction kernel's average launch time (HIP events) per
+    operand set."""
+    import dataclasses
+    import torch
+    import synthcells
+    from paper_1602_06589_amd import Flapw
+    cell = synthcells.config(config, n_k=1)
+    cell = dataclasses.replace(cell, ud_norm2=np.ones_like(cell.ud_norm2))
+    n, kr = cell.n_g(0), cell.k_rows()
+    gen = torch.Generator(device="cuda").manual_seed(1602)
+    res = {"workload": cell.name, "K": kr, "n_g": n, "slices": slices}
+    with Flapw() as fl:
+        ldt = 2 * int((cell.lmax.max() + 1) ** 2)
+        T = torch.eye(ldt, dtype=torch.complex128, device="cuda").repeat(cell.n_types, 1, 1).contiguous()
+        H = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+        S = torch.zeros_like(H)
+        for kind in ("random", "constant"):
+            if kind == "random":
+                A = torch.randn((n, kr), dtype=torch.complex128, device="cuda", generator=gen)
+                B = torch.randn((n, kr), dtype=torch.complex128, device="cuda", generator=gen)
+            else:
+                A = torch.full((n, kr), complex(1.0, 1.0), dtype=torch.complex128, device="cuda")
+                B = torch.full_like(A, complex(1.0, 1.0))
+            fl.hs_contract(cell, A, B, T, prec="i8mod", slices=slices, H=H, S=S)       # warm-up
+            torch.cuda.synchronize()
+            fl.profile(True)
+            for _ in range(reps):
+                fl.hs_contract(cell, A, B, T, prec="i8mod", slices=slices, H=H, S=S)
+            torch.cuda.synchronize()
+            nl, ms = fl.kernel_time("hs_mod")
+            fl.profile(False)
+            res[kind + "_ms"] = ms / max(1, nl)
+            print(f"# operand study {kind}: hs_mod {ms / max(1, nl):.1f} ms per launch", flush=True)
+            del A, B
+            torch.cuda.empty_cache()
+    res["random_over_constant"] = res["random_ms"] / res["constant_ms"]
+    return res
+
+
 def make_parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +301,9 @@ def make_parser() -> argparse.ArgumentParser:
                     help="mesh points of the radial-setup leg (radial functions and integrals of the "
                          "workload's atom types); 0 skips the leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--operand-study", action="store_true",
+                    help="only time the modular contraction of one k-point-sized problem on random and on constant "
+                         "operands (same instructions, different switching activity) and exit")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (calibrates the "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters against known bytes) and exit")
@@ -267,6 +316,9 @@ def main():
 
     if args.mfma_ceiling:
         print(json.dumps(mfma_ceiling()))
+        return
+    if args.operand_study:
+        print(json.dumps(operand_study(args.config, args.slices or 11)))
         return
     if args.copy_calib:
         import torch

@@ -148,6 +148,12 @@ long long flapw_workspace_bytes(flapw_handle h);
  * that needs them; nothing in them outlives a call.  Waits for the device first, as
  * flapw_destroy does; plans keep their own buffers.  Errors: FLAPW_ERR_ARG for a NULL handle. */
 flapw_status flapw_release_workspace(flapw_handle h);
+/* Workspace watermark: after every flapw_hs_generate, flapw_hs_contract, flapw_s_legendre or
+ * flapw_interstitial call that leaves the handle's work buffers above `bytes`, the call waits for
+ * its stream and frees them (as flapw_release_workspace), so that one handle's buffers do not
+ * crowd out other handles or the caller's allocations between calls.  bytes < 0 (the default):
+ * no limit, buffers are kept for the next call.  Errors: FLAPW_ERR_ARG for a NULL handle. */
+flapw_status flapw_set_workspace_limit(flapw_handle h, long long bytes);
 
 /* Matching coefficients A_* and B_* of one k-point (appendix A.1, eqs. def_a_tensor,
  * def_b_tensor; Wronskian W = udot u' - u udot'; stacked layout of section 4.2).
@@ -353,29 +359,31 @@ flapw_status flapw_plan_destroy(flapw_plan plan);
 /* Autotuner.  Chooses, for one k-point (k, n_g G vectors, device list g), the digit or modulus
  * count of the split path and the tile band of the contraction (the number of tile rows one band
  * of the launch order walks; neighbouring work-groups of a band share their row panel in L2).
- *   count:  the first n = min(n_g, 1024) columns are generated with FP64 and with 3, 4, 5, 6 digits
- *           (SPLIT_I8, SPLIT_BF16) or 10, 11, 12, 13 moduli (SPLIT_I8_MOD).  The relative
- *           Frobenius errors of H and S on those n x n upper triangles (against the FP64 result)
- *           are extrapolated to the whole matrix by the factor sqrt(n_g / n): the rounding error of
- *           every entry scales with the norms of its two operand columns, so the error mass grows
- *           with the n_g^2 entries while the matrices' own mass sits near the diagonal and grows
- *           with n_g.  The smallest count whose extrapolated errors are both <= tol / 2 is chosen.
- *           FP64: 0.
- *   band:   a prefix of at most 8192 tiles of the contraction of the whole k-point is timed
- *           with HIP events for bands 1, 2, 4, 8, 16; the fastest is chosen.
+ *   count:  a seeded uniform random subset of n = min(n_g, 1024) basis functions is generated with
+ *           FP64 and with 3, 4, 5, 6 digits (SPLIT_I8, SPLIT_BF16) or 10, 11, 12, 13 moduli
+ *           (SPLIT_I8_MOD).  From the n x n principal submatrices of H and S the relative
+ *           Frobenius error of each whole n_g x n_g matrix is estimated without bias (the sampled
+ *           diagonal entries weighted by n_g / n, the sampled pairs by n_g (n_g - 1) / (n (n - 1)),
+ *           in the squared norms of the error and of the FP64 result); the smallest count whose
+ *           estimates for H and S are both <= 2 tol / 3 is chosen.  FP64: 0.
+ *   band and stage depth:  a prefix of at most 8192 tiles of the contraction of the whole k-point
+ *           is timed with HIP events for bands 1, 2, 4, 8, 16 and, for SPLIT_I8_MOD, each with
+ *           64-row and with 32-row LDS stages of the contraction kernel; the fastest is chosen.
  * The choice is stored in the handle under (prec, padded contraction rows of the atom set as the
  * generation lays them out, S method, lnonsph) and used by later flapw_hs_generate /
  * flapw_plan_create calls with slices = 0 (band: every call) under the same handle settings and
  * atom set, and by flapw_hs_contract when it was tuned with the default settings (S_GEMM, dense T).
- * Outputs: *slices, *band; digit_err[4] (the extrapolated errors of the four candidate counts,
- * NaN where not evaluated) and band_ms[5] (prefix times for bands 1, 2, 4, 8, 16) when not NULL.
+ * Outputs: *slices, *band; *stage_rows (64 or 32 for SPLIT_I8_MOD, else 0) when not NULL;
+ * digit_err[4] (the estimated errors of the four candidate counts, NaN where not evaluated) and
+ * band_ms[10] (prefix times for bands 1, 2, 4, 8, 16 with 64-row stages, then with 32-row stages;
+ * NaN where not timed) when not NULL.
  * Runs synchronously on the null stream and allocates temporary device memory for two n_g x n_g
  * outputs (freed before returning).  Errors: as flapw_hs_generate; FLAPW_ERR_ARG for tol <= 0;
  * FLAPW_ERR_UNSUPPORTED when no candidate count meets tol (digit_err is still filled) or for
  * FLAPW_PREC_SPLIT_FP32. */
 flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
                         const flapw_radial *rad, const flapw_potential *pot, flapw_prec prec, double tol, int *slices,
-                        int *band, double *digit_err, double *band_ms);
+                        int *band, int *stage_rows, double *digit_err, double *band_ms);
 
 /* Kernel timing for profiling (off by default).  While enabled, the library records a pair of
  * HIP events on the launch stream around every launch of its kernels.  flapw_profile_query

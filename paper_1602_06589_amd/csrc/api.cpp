@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -456,6 +457,11 @@ const flapw_context::Tuned *find_tuned(flapw_handle h, flapw_prec prec, long lon
     return nullptr;
 }
 
+// The tuner accepts a digit or modulus count whose estimated whole-matrix errors are at most this
+// fraction of the tolerance (room for the k-points it does not sample, whose errors grow like the
+// square root of their basis size).
+constexpr double kTuneMargin = 2.0 / 3.0;
+
 // slices == 0: the tuned digit count for the key, else the library default
 int effective_slices(flapw_handle h, flapw_prec prec, long long kp2, int s_method, int lnonsph, int slices)
 {
@@ -469,6 +475,16 @@ int effective_band(flapw_handle h, flapw_prec prec, long long kp2, int s_method,
 {
     const auto *t = find_tuned(h, prec, kp2, s_method, lnonsph);
     return t ? t->band : 4;
+}
+
+// 16-row chunks per LDS stage of the modular contraction: the tuned count, else 4 (64-row stages;
+// the environment variable FLAPW_MOD_STAGE_ROWS = 32 selects 32-row stages instead)
+int effective_chunks(flapw_handle h, flapw_prec prec, long long kp2, int s_method, int lnonsph)
+{
+    const auto *t = find_tuned(h, prec, kp2, s_method, lnonsph);
+    if (t && t->chunks) return t->chunks;
+    const char *env = std::getenv("FLAPW_MOD_STAGE_ROWS");
+    return env && std::atoi(env) == 32 ? 2 : 4;
 }
 
 // Digit storage of one problem inside a digit buffer.
@@ -497,7 +513,7 @@ DigitArea digit_area(void *base, long long kp2, long long np, int s, int eb)
 // column exponents, and the residue tiles.
 struct ModArea {
     int8_t *L, *RS, *RH;
-    int *eL, *eRS, *eRH;
+    double *sL, *sRS, *sRH;
     int8_t *res;
     long long npm;
 };
@@ -505,21 +521,21 @@ struct ModArea {
 long long mod_area_bytes(long long kp2, long long np, int nm)
 {
     const long long npm = round_up(np, 2 * kModTile);
-    return 3 * round_up(mod_digit_bytes(kp2, npm, nm), 256) + 3 * round_up(npm * 4, 256) +
+    return 3 * round_up(mod_digit_bytes(kp2, npm, nm), 256) + 3 * round_up(npm * 8, 256) +
            round_up(mod_scratch_bytes(npm, nm), 256);
 }
 
 ModArea mod_area(void *base, long long kp2, long long np, int nm)
 {
     const long long npm = round_up(np, 2 * kModTile);
-    const long long one = round_up(mod_digit_bytes(kp2, npm, nm), 256), ex = round_up(npm * 4, 256);
+    const long long one = round_up(mod_digit_bytes(kp2, npm, nm), 256), ex = round_up(npm * 8, 256);
     unsigned char *b = (unsigned char *)base;
     return ModArea{(int8_t *)b,
                    (int8_t *)(b + one),
                    (int8_t *)(b + 2 * one),
-                   (int *)(b + 3 * one),
-                   (int *)(b + 3 * one + ex),
-                   (int *)(b + 3 * one + 2 * ex),
+                   (double *)(b + 3 * one),
+                   (double *)(b + 3 * one + ex),
+                   (double *)(b + 3 * one + 2 * ex),
                    (int8_t *)(b + 3 * one + 3 * ex),
                    npm};
 }
@@ -527,7 +543,7 @@ ModArea mod_area(void *base, long long kp2, long long np, int nm)
 ModProblemDev mod_problem(const ModArea &ma, double2 *H, double2 *S, long long ldh, int n, long long kp2)
 {
     const long long t = ma.npm / kModTile;
-    return ModProblemDev{ma.L, ma.RS, ma.RH, ma.eL, ma.eRS, ma.eRH, H, S, ma.res, ldh, n, (int)kp2,
+    return ModProblemDev{ma.L, ma.RS, ma.RH, ma.sL, ma.sRS, ma.sRH, H, S, ma.res, ldh, n, (int)kp2,
                          (int)(ma.npm / 32), (int)(t * (t + 1) / 2)};
 }
 
@@ -535,7 +551,7 @@ flapw_status mod_slice_problem(flapw_handle h, const ProblemDev &pb, long long n
                                const ModTable &mt, bool with_s, const double *part, long long n_slots, hipStream_t st)
 {
     ProfScope prof(h, "slice", st);
-    hipError_t e = launch_mod_slice(pb.P, pb.Q, pb.d, pb.ldp, pb.kp2, (int)np, (int)ma.npm, mt, ma.eL, ma.eRS, ma.eRH,
+    hipError_t e = launch_mod_slice(pb.P, pb.Q, pb.d, pb.ldp, pb.kp2, (int)np, (int)ma.npm, mt, ma.sL, ma.sRS, ma.sRH,
                                     ma.L, ma.RS, ma.RH, with_s, part, n_slots, st);
     if (e != hipSuccess) return dev_fail(h, e, "residue slicing kernels");
     return FLAPW_OK;
@@ -544,12 +560,12 @@ flapw_status mod_slice_problem(flapw_handle h, const ProblemDev &pb, long long n
 // Modular contraction of a batch: residues per (256 x 128 block, modulus), then the CRT
 // reconstruction per 128 x 128 tile.
 hipError_t launch_mod_pair(flapw_handle h, const ModProblemDev *probs, const TileDev *blocks, int n_blocks,
-                           const TileDev *tiles, int n_tiles, const ModTable &mt, hipStream_t st)
+                           const TileDev *tiles, int n_tiles, const ModTable &mt, int chunks, hipStream_t st)
 {
     hipError_t e;
     {
         ProfScope prof(h, "hs_mod", st);
-        e = launch_mod_contract(probs, blocks, n_blocks, mt, st);
+        e = launch_mod_contract(probs, blocks, n_blocks, mt, chunks, st);
     }
     if (e != hipSuccess) return e;
     ProfScope prof(h, "mod_crt", st);
@@ -641,6 +657,7 @@ struct GenPlan {
     int lh0 = 1 << 20;           // the Legendre kernel adds to H the L-diagonal terms of l >= lh0
     double omega = 0.0;
     int sl = 0, band = 4;
+    int chunks = 4;              // modular contraction: 16-row chunks per LDS stage
     long long ldt = 0;
     double pref = 0.0;
     int n_atoms = 0, n_types = 0;
@@ -730,6 +747,7 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
     p.sl = effective_slices(h, prec, L.kp2, smeth, p.lnonsph, slices);
     if (p.mod) p.mt = make_mod_table(p.sl);
     p.band = band ? band : effective_band(h, prec, L.kp2, smeth, p.lnonsph);
+    p.chunks = effective_chunks(h, prec, L.kp2, smeth, p.lnonsph);
     p.ldt = 2LL * L.nlmax;
     p.pref = 4.0 * kPi / std::sqrt(at->omega);
     p.kv.assign(k, k + 3 * (size_t)n_k);
@@ -978,7 +996,7 @@ flapw_status enqueue_generate(flapw_handle h, const GenPlan &p, hipStream_t s)
         hipError_t e;
         if (p.mod) {
             e = launch_mod_pair(h, (const ModProblemDev *)(p.desc + bt.o_probs), (const TileDev *)(p.desc + bt.o_tiles),
-                                bt.n_tiles, (const TileDev *)(p.desc + bt.o_ctiles), bt.n_ctiles, p.mt, s);
+                                bt.n_tiles, (const TileDev *)(p.desc + bt.o_ctiles), bt.n_ctiles, p.mt, p.chunks, s);
         } else if (p.split) {
             ProfScope prof(h, "hs_split", s);
             e = launch_split_any(p.bf16, (const SplitProblemDev *)(p.desc + bt.o_probs),
@@ -1035,7 +1053,7 @@ flapw_status time_contraction(flapw_handle h, const GenPlan &p, int cap, float *
         e = hipEventRecord(e0, nullptr);
         if (e == hipSuccess)
             e = p.mod     ? launch_mod_contract((const ModProblemDev *)(p.desc + bt.o_probs),
-                                                (const TileDev *)(p.desc + bt.o_tiles), n, p.mt, nullptr)
+                                                (const TileDev *)(p.desc + bt.o_tiles), n, p.mt, p.chunks, nullptr)
                 : p.split ? launch_split_any(p.bf16, (const SplitProblemDev *)(p.desc + bt.o_probs),
                                              (const TileDev *)(p.desc + bt.o_tiles), n, p.sl, nullptr)
                           : launch_hs_fp64((const ProblemDev *)(p.desc + bt.o_probs),
@@ -1050,16 +1068,23 @@ flapw_status time_contraction(flapw_handle h, const GenPlan &p, int cap, float *
     return FLAPW_OK;
 }
 
-// Relative Frobenius error of the upper triangles (with diagonal) of two n x n column-major matrices.
-double upper_relfro(const std::vector<double2> &got, const std::vector<double2> &ref, int n)
+// Relative Frobenius error of a whole N x N Hermitian matrix estimated from its principal submatrix
+// on a uniform random subset of n indices (upper triangles of two n x n column-major matrices): the
+// n diagonal entries stand for the N diagonal entries (weight N/n), the n(n-1)/2 pairs t' < t for
+// the N(N-1)/2 pairs (weight N(N-1)/(n(n-1)), counted twice for the Hermitian lower half), in the
+// squared norms of the error and of the reference.  With n = N it is the matrix's own error.
+double sampled_relfro(const std::vector<double2> &got, const std::vector<double2> &ref, int n, int N)
 {
-    double num = 0.0, den = 0.0;
+    double ed = 0.0, eo = 0.0, rd = 0.0, ro = 0.0;
     for (int j = 0; j < n; ++j)
         for (int i = 0; i <= j; ++i) {
             const double2 a = got[(size_t)j * n + i], b = ref[(size_t)j * n + i];
-            num += (a.x - b.x) * (a.x - b.x) + (a.y - b.y) * (a.y - b.y);
-            den += b.x * b.x + b.y * b.y;
+            const double e2 = (a.x - b.x) * (a.x - b.x) + (a.y - b.y) * (a.y - b.y), r2 = b.x * b.x + b.y * b.y;
+            if (i == j) ed += e2, rd += r2;
+            else eo += e2, ro += r2;
         }
+    const double wd = (double)N / n, wo = n > 1 ? (double)N * (N - 1.0) / ((double)n * (n - 1.0)) : 0.0;
+    const double num = wd * ed + 2.0 * wo * eo, den = wd * rd + 2.0 * wo * ro;
     return den > 0.0 ? std::sqrt(num / den) : std::sqrt(num);
 }
 
@@ -1079,6 +1104,38 @@ struct TuneScratch {
     }
 };
 
+
+// The handle's work buffers: their bytes, and releasing them (the grow-only buffers the next call
+// allocates again).
+long long ws_bytes(flapw_handle h)
+{
+    return (long long)(h->work.n + h->tmat.n + h->tables.n + h->gaunt.n + h->tiles.n + h->leg.n + h->eig.n) +
+           split_bytes(h);
+}
+
+void ws_release(flapw_handle h)
+{
+    h->work.release();
+    h->tmat.release();
+    h->tables.release();
+    h->gaunt.release();
+    h->tiles.release();
+    h->leg.release();
+    h->radial.release();
+    h->eig.release();
+    split_release(h);
+}
+
+// After a computing call that succeeded: with a workspace limit set and the handle's buffers above
+// it, wait for the call's work on its stream and free them.
+flapw_status trim_workspace(flapw_handle h, hipStream_t s, flapw_status st)
+{
+    if (st != FLAPW_OK || h->ws_limit < 0 || ws_bytes(h) <= h->ws_limit) return st;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return dev_fail(h, e, "waiting to release the workspace");
+    ws_release(h);
+    return st;
+}
 
 // ------------------------------------------------------------------------ no-allocation scratch
 
@@ -1279,7 +1336,8 @@ flapw_status hs_contract_impl(flapw_handle h, int n_g, const flapw_atoms *at, co
         const size_t ot = put(hs, tiles.data(), tiles.size());
         if ((st = bufs.upload(h->sdesc, hs, s, &db)) != FLAPW_OK) return st;
         e = launch_mod_pair(h, (const ModProblemDev *)(db + op), (const TileDev *)(db + ob), (int)blocks.size(),
-                            (const TileDev *)(db + ot), (int)tiles.size(), mt, s);
+                            (const TileDev *)(db + ot), (int)tiles.size(), mt,
+                            effective_chunks(h, prec, L.kp2, FLAPW_S_GEMM, -1), s);
         if (e != hipSuccess) return dev_fail(h, e, "S/H modular split kernels");
         return FLAPW_OK;
     }
@@ -1369,7 +1427,7 @@ const char *flapw_last_error(flapw_handle h) { return h ? h->err.c_str() : "NULL
 
 flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
                         const flapw_radial *rad, const flapw_potential *pot, flapw_prec prec, double tol, int *slices,
-                        int *band, double *digit_err, double *band_ms)
+                        int *band, int *stage_rows, double *digit_err, double *band_ms)
 {
     if (!h) return FLAPW_ERR_ARG;
     if (!slices || !band) return fail(h, FLAPW_ERR_ARG, "NULL pointer argument");
@@ -1379,7 +1437,7 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
     flapw_status st = check_generate(h, 1, k, &n_g, &g, at, rad, pot, &dummy, &dummy, &ld1, prec, 0);
     if (st != FLAPW_OK) return st;
     for (int i = 0; digit_err && i < 4; ++i) digit_err[i] = std::nan("");
-    for (int i = 0; band_ms && i < 5; ++i) band_ms[i] = std::nan("");
+    for (int i = 0; band_ms && i < 10; ++i) band_ms[i] = std::nan("");
     const bool split = prec != FLAPW_PREC_FP64;
     // the gate and the timing cover the muffin-tin parts (the interstitial terms are FP64 either way)
     struct InterOff {
@@ -1394,8 +1452,27 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
     GenBuffers b{&h->tmat,        &h->tables,      &h->gaunt,     &h->tiles,     &h->work, &h->digits,
                  &h->leg,         &h->host_tables, &h->host_gaunt, &h->host_tiles};
     if (split) {
-        // accuracy gate on the first n_acc columns (the shortest k+G), against the FP64 path
+        // accuracy gate on a random subset of n_acc basis functions (seeded, so the choice is
+        // reproducible), against the FP64 path on the same subset
         const int n_acc = std::min(n_g, 1024);
+        std::vector<int> pick(n_g);
+        for (int i = 0; i < n_g; ++i) pick[i] = i;
+        if (n_acc < n_g) {
+            std::mt19937_64 rng(0x1602065890ULL);
+            for (int i = 0; i < n_acc; ++i) std::swap(pick[i], pick[i + (int)(rng() % (unsigned long long)(n_g - i))]);
+            pick.resize(n_acc);
+            std::sort(pick.begin(), pick.end());
+        }
+        std::vector<double> gall((size_t)3 * n_g), gsub((size_t)3 * n_acc);
+        if ((e = hipMemcpy(gall.data(), g, gall.size() * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)
+            return dev_fail(h, e, "reading the G list");
+        for (int i = 0; i < n_acc; ++i)
+            for (int c = 0; c < 3; ++c) gsub[3 * i + c] = gall[3 * (size_t)pick[i] + c];
+        void *gs = nullptr;
+        if ((e = scratch.alloc(&gs, gsub.size() * sizeof(double))) != hipSuccess ||
+            (e = hipMemcpy(gs, gsub.data(), gsub.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+            return dev_fail(h, e, "uploading the sampled G list");
+        const double *gsd = (const double *)gs;
         const size_t mat = (size_t)n_acc * n_acc * sizeof(double2);
         void *buf[4];
         for (int i = 0; i < 4; ++i)
@@ -1409,21 +1486,18 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
             const int s = cand[ci];
             flapw_z *Hp = (flapw_z *)buf[s ? 2 : 0], *Sp = (flapw_z *)buf[s ? 3 : 1];
             GenPlan p;
-            st = prepare_generate(h, 1, k, &n_acc, &g, at, rad, pot, &Hp, &Sp, &ldn, s ? prec : FLAPW_PREC_FP64, s, 4, false, b,
-                                  p, nullptr, false);
+            st = prepare_generate(h, 1, k, &n_acc, &gsd, at, rad, pot, &Hp, &Sp, &ldn, s ? prec : FLAPW_PREC_FP64, s, 4,
+                                  false, b, p, nullptr, false);
             if (st == FLAPW_OK) st = enqueue_generate(h, p, nullptr);
             if (st != FLAPW_OK) return st;
             e = hipMemcpy((s ? Hc : Hr).data(), Hp, mat, hipMemcpyDeviceToHost);
             if (e == hipSuccess) e = hipMemcpy((s ? Sc : Sr).data(), Sp, mat, hipMemcpyDeviceToHost);
             if (e != hipSuccess) return dev_fail(h, e, "reading tuner outputs");
             if (!s) continue;
-            // extrapolated to the whole matrix: the error of an entry scales with the norms of its two
-            // operand columns, so the error mass grows with the n_g^2 entries, the matrices' own mass
-            // (near the diagonal) with n_g
-            const double err = std::max(upper_relfro(Hc, Hr, n_acc), upper_relfro(Sc, Sr, n_acc)) *
-                               std::sqrt((double)n_g / (double)n_acc);
+            // the whole matrix's relative Frobenius error, estimated without bias from the sample
+            const double err = std::max(sampled_relfro(Hc, Hr, n_acc, n_g), sampled_relfro(Sc, Sr, n_acc, n_g));
             if (digit_err) digit_err[ci - 1] = err;
-            if (!chosen && err <= 0.5 * tol) chosen = s;
+            if (!chosen && err <= kTuneMargin * tol) chosen = s;
         }
         if (!chosen)
             return fail(h, FLAPW_ERR_UNSUPPORTED, prec == FLAPW_PREC_SPLIT_I8_MOD
@@ -1436,21 +1510,23 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
     if ((e = scratch.alloc(&Hb, mat)) != hipSuccess || (e = scratch.alloc(&Sb, mat)) != hipSuccess)
         return dev_fail(h, e, "allocating tuner outputs");
     static const int bands[5] = {1, 2, 4, 8, 16};
-    int best = 4;
+    const bool mod = prec == FLAPW_PREC_SPLIT_I8_MOD;
+    int best = 4, best_chunks = 0;
     float best_ms = 0.0f;
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < (mod ? 10 : 5); ++i) {
         flapw_z *Hp = (flapw_z *)Hb, *Sp = (flapw_z *)Sb;
         GenPlan p;
-        st = prepare_generate(h, 1, k, &n_g, &g, at, rad, pot, &Hp, &Sp, &ld1, prec, chosen, bands[i],
+        st = prepare_generate(h, 1, k, &n_g, &g, at, rad, pot, &Hp, &Sp, &ld1, prec, chosen, bands[i % 5],
                               h->s_method == FLAPW_S_LEGENDRE, b, p, nullptr,
                               false);
         if (st == FLAPW_OK && i == 0) st = enqueue_generate(h, p, nullptr);   // panels / digits for the timing
         if (st != FLAPW_OK) return st;
         if (p.batches.size() != 1) return fail(h, FLAPW_ERR_NOMEM, "one k-point does not fit the work budget");
+        p.chunks = i < 5 ? 4 : 2;                       // the modular path: 64-row, then 32-row stages
         float ms = 0.0f;
         if ((st = time_contraction(h, p, 8192, &ms)) != FLAPW_OK) return st;
         if (band_ms) band_ms[i] = ms;
-        if (i == 0 || ms < best_ms) best_ms = ms, best = bands[i];
+        if (i == 0 || ms < best_ms) best_ms = ms, best = bands[i % 5], best_chunks = mod ? p.chunks : 0;
     }
     // keyed as prepare_generate looks it up: the row layout with the same cut, the S method, lnonsph
     Layout L;
@@ -1458,13 +1534,15 @@ flapw_status flapw_tune(flapw_handle h, const double *k, int n_g, const double *
     for (int t = 0; t < rad->n_types; ++t) lmx = std::max(lmx, rad->lmax[t]);
     const bool leg = h->s_method == FLAPW_S_LEGENDRE;
     build_layout(at, rad, true, L, (leg && h->lnonsph >= 0 && h->lnonsph < lmx) ? h->lnonsph : -1);
-    flapw_context::Tuned t{(int)prec, L.kp2, leg ? (int)FLAPW_S_LEGENDRE : (int)FLAPW_S_GEMM, h->lnonsph, chosen, best};
+    flapw_context::Tuned t{(int)prec, L.kp2, leg ? (int)FLAPW_S_LEGENDRE : (int)FLAPW_S_GEMM, h->lnonsph, chosen, best,
+                           best_chunks};
     bool found = false;
     for (auto &x : h->tuned)
         if (x.prec == t.prec && x.kp2 == t.kp2 && x.s_method == t.s_method && x.lnonsph == t.lnonsph) x = t, found = true;
     if (!found) h->tuned.push_back(t);
     *slices = chosen;
     *band = best;
+    if (stage_rows) *stage_rows = 16 * best_chunks;
     return FLAPW_OK;
 }
 
@@ -1512,22 +1590,21 @@ flapw_status flapw_release_workspace(flapw_handle h)
 {
     if (!h) return FLAPW_ERR_ARG;
     if (h->device >= 0) (void)hipDeviceSynchronize();
-    h->work.release();
-    h->tmat.release();
-    h->tables.release();
-    h->gaunt.release();
-    h->tiles.release();
-    h->leg.release();
-    h->radial.release();
-    split_release(h);
-    h->eig.release();
+    ws_release(h);
+    return FLAPW_OK;
+}
+
+flapw_status flapw_set_workspace_limit(flapw_handle h, long long bytes)
+{
+    if (!h) return FLAPW_ERR_ARG;
+    h->ws_limit = bytes < 0 ? -1 : bytes;
     return FLAPW_OK;
 }
 
 long long flapw_workspace_bytes(flapw_handle h)
 {
     if (!h) return -1;
-    return (long long)(h->work.n + h->tmat.n + h->tables.n + h->gaunt.n + h->tiles.n + h->leg.n) + split_bytes(h);
+    return ws_bytes(h);
 }
 
 flapw_status flapw_coeffs(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
@@ -1578,7 +1655,9 @@ flapw_status flapw_hs_contract(flapw_handle h, int n_g, const flapw_atoms *at, c
                                const flapw_z *A, const flapw_z *B, long lda, const flapw_z *T, long ldt, flapw_z *H,
                                flapw_z *S, long ldh, flapw_prec prec, int slices, flapw_stream stream)
 {
-    return hs_contract_impl(h, n_g, at, rad, A, B, lda, T, ldt, H, S, ldh, prec, slices, stream, false);
+    if (!h) return FLAPW_ERR_ARG;
+    return trim_workspace(h, (hipStream_t)stream,
+                          hs_contract_impl(h, n_g, at, rad, A, B, lda, T, ldt, H, S, ldh, prec, slices, stream, false));
 }
 
 flapw_status flapw_hs_contract_noalloc(flapw_handle h, int n_g, const flapw_atoms *at, const flapw_radial *rad,
@@ -1606,7 +1685,7 @@ flapw_status flapw_hs_generate(flapw_handle h, int n_k, const double *k, const i
     st = prepare_generate(h, n_k, k, n_g, g, at, rad, pot, H, S, ldh, prec, slices, 0, h->s_method == FLAPW_S_LEGENDRE,
                           b, p, s, false);
     if (st != FLAPW_OK) return st;
-    return enqueue_generate(h, p, s);
+    return trim_workspace(h, s, enqueue_generate(h, p, s));
 }
 
 flapw_status flapw_set_s_method(flapw_handle h, flapw_s_method method)
@@ -1670,7 +1749,7 @@ flapw_status flapw_s_legendre(flapw_handle h, const double *k, int n_g, const do
     hipError_t e = h->leg.ensure(leg_bytes(L, p.np[0], p.n_types, &p.leg_ab, &p.leg_E));
     if (e != hipSuccess) return dev_fail(h, e, "allocating Legendre scratch");
     p.legbuf = (unsigned char *)h->leg.p;
-    return enqueue_s_legendre(h, p, 0, (double2 *)S, lds, s);
+    return trim_workspace(h, s, enqueue_s_legendre(h, p, 0, (double2 *)S, lds, s));
 }
 
 flapw_status flapw_interstitial(flapw_handle h, const double *k, int n_g, const double *g, const flapw_atoms *at,
@@ -1722,7 +1801,7 @@ flapw_status flapw_interstitial(flapw_handle h, const double *k, int n_g, const 
     hipError_t e = h->leg.ensure(leg_bytes(L, p.np[0], p.n_types, &p.leg_ab, &p.leg_E));
     if (e != hipSuccess) return dev_fail(h, e, "allocating phase scratch");
     p.legbuf = (unsigned char *)h->leg.p;
-    return enqueue_interstitial(h, p, 0, true, s);
+    return trim_workspace(h, s, enqueue_interstitial(h, p, 0, true, s));
 }
 
 flapw_status flapw_set_interstitial(flapw_handle h, int on, const double *lattice, double v_int)

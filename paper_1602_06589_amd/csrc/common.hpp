@@ -162,13 +162,19 @@ hipError_t launch_interstitial(const double *g, const double kvec[3], const doub
                                long long ldh, hipStream_t s);
 
 // Modular split precision (split_mod.hip).  Moduli p_m, 1/p_m as double-double, the CRT
-// constants w_m = (M/p_m)^-1 mod p_m, M = prod p_m as double-double, and the integer bits B.
+// constants w_m = (M/p_m)^-1 mod p_m, M = prod p_m as double-double, and the integer range: the
+// column norm 2^B the operands are scaled to (bits_real = B, bits = floor(B), two2b = 2^B).
 constexpr int kModCap = 14;
 constexpr int kModMin = 8;
 constexpr int kModTile = 128;   // output tile edge of the modular contraction
+constexpr int kResTileBytes = kModTile * kModTile * 2;  // int8 residues of Re and Im of one tile
+// slot of upper-triangle tile (ti <= tj) in the residue scratch of one matrix
+__host__ __device__ inline int tri_index(int ti, int tj) { return tj * (tj + 1) / 2 + ti; }
 struct ModTable {
     int nm;
     int bits;
+    double bits_real;
+    double two2b;
     int p[kModCap];
     int w[kModCap];
     double inv_p[kModCap];
@@ -179,7 +185,7 @@ struct ModTable {
 // ncb 32-column blocks wide; res: residue tiles, 2 ntri slots per modulus (S tiles, then H).
 struct ModProblemDev {
     const int8_t *L, *RS, *RH;
-    const int *eL, *eRS, *eRH;
+    const double *sL, *sRS, *sRH;     // column scales (integers = rint(value * scale))
     double2 *H, *S;
     int8_t *res;
     long long ldh;
@@ -195,10 +201,11 @@ long long mod_scratch_bytes(long long npm, int nm);
 // with_s = false: no S operand.  part: the column-sum shares of the real-T panel kernel over
 // n_slots (atom, row tile) slots, or nullptr to read the column norms from P and Q.
 hipError_t launch_mod_slice(const double2 *P, const double2 *Q, const double *d, long long ld, int kp2, int np,
-                            int npm, const ModTable &mt, int *eL, int *eRS, int *eRH, int8_t *L, int8_t *RS,
+                            int npm, const ModTable &mt, double *sL, double *sRS, double *sRH, int8_t *L, int8_t *RS,
                             int8_t *RH, bool with_s, const double *part, long long n_slots, hipStream_t s);
+// chunks: 16-row chunks per LDS stage of the contraction kernel (4 or 2)
 hipError_t launch_mod_contract(const ModProblemDev *probs, const TileDev *tiles, int n_tiles, const ModTable &mt,
-                               hipStream_t s);
+                               int chunks, hipStream_t s);
 hipError_t launch_mod_crt(const ModProblemDev *probs, const TileDev *tiles, int n_tiles, const ModTable &mt,
                           hipStream_t s);
 

@@ -67,6 +67,7 @@ struct flapw_context {
     double v_int = 0.0;
     double lattice[9] = {};
     void *blas = nullptr;      // rocblas_handle of flapw_eigensolve (created on first use)
+    long long ws_limit = -1;   // flapw_set_workspace_limit: free the work buffers above it after a call
     flapw::DevBuf eig;         // flapw_eigensolve: off-diagonal workspace and status word
     std::vector<unsigned char> host_tables, host_gaunt, host_tiles, host_sdesc;
     std::vector<long long> host_src;
@@ -79,6 +80,7 @@ struct flapw_context {
         int lnonsph;
         int slices;
         int band;
+        int chunks;            // modular contraction: 16-row chunks per LDS stage (0: not tuned)
     };
     std::vector<Tuned> tuned;
     // profiling: event pairs per kernel family, recorded while `profiling` is set

@@ -40,7 +40,7 @@ EXPORTS = ["flapw_create", "flapw_destroy", "flapw_status_string", "flapw_last_e
            "flapw_set_lnonsph", "flapw_s_legendre", "flapw_plan_create",
            "flapw_plan_launch", "flapw_plan_destroy", "flapw_tune", "flapw_profile_enable", "flapw_profile_query",
            "flapw_radial_setup", "flapw_hs_contract_noalloc", "flapw_noalloc_scratch_bytes", "flapw_interstitial",
-           "flapw_set_interstitial", "flapw_eigensolve"]
+           "flapw_set_interstitial", "flapw_eigensolve", "flapw_set_workspace_limit"]
 
 
 class FlapwError(RuntimeError):
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         lib.flapw_workspace_bytes.argtypes = [P]
         lib.flapw_workspace_bytes.restype = ctypes.c_longlong
         lib.flapw_release_workspace.argtypes = [P]
+        lib.flapw_set_workspace_limit.argtypes = [P, ctypes.c_longlong]
         lib.flapw_release_workspace.restype = ctypes.c_int
         lib.flapw_coeffs.argtypes = [P, P, I, P, P, P, P, P, L, P]
         lib.flapw_build_T.argtypes = [P, P, P, P, L, P]
@@ -108,7 +109,8 @@ def load_library(path: str = LIB_PATH):
         lib.flapw_plan_launch.argtypes = [P, P]
         lib.flapw_plan_destroy.argtypes = [P]
         D = ctypes.POINTER(ctypes.c_double)
-        lib.flapw_tune.argtypes = [P, P, I, P, P, P, P, I, ctypes.c_double, ctypes.POINTER(I), ctypes.POINTER(I), D, D]
+        lib.flapw_tune.argtypes = [P, P, I, P, P, P, P, I, ctypes.c_double, ctypes.POINTER(I), ctypes.POINTER(I),
+                                   ctypes.POINTER(I), D, D]
         lib.flapw_profile_enable.argtypes = [P, I]
         lib.flapw_profile_query.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_double)]
         lib.flapw_radial_setup.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
@@ -205,6 +207,10 @@ class Flapw:
     def release_workspace(self):
         """Free the handle's work buffers (the next call allocates what it needs again)."""
         self._check(self._lib.flapw_release_workspace(self._h))
+
+    def set_workspace_limit(self, nbytes: int = -1):
+        """After a call that leaves the work buffers above nbytes, wait and free them (-1: keep)."""
+        self._check(self._lib.flapw_set_workspace_limit(self._h, int(nbytes)))
 
     # --------------------------------------------------------------------- descriptors
     def _radial(self, s):
@@ -382,18 +388,20 @@ class Flapw:
 
     def tune(self, system, k, g, prec="i8", tol: float = 1e-10):
         """Runs the autotuner on one k-point (g: device tensor (n_g, 3)); the handle keeps the choice.
-        Returns {"slices", "band", "digit_err" (3..6 digits, or 10..13 moduli for "i8mod"),
-        "band_ms" (bands 1, 2, 4, 8, 16)}."""
+        Returns {"slices", "band", "stage_rows" (modular path: 64 or 32, else 0), "digit_err"
+        (estimated whole-matrix errors for 3..6 digits, or 10..13 moduli for "i8mod"), "band_ms"
+        (bands 1, 2, 4, 8, 16 with 64-row stages, then with 32-row stages for "i8mod")}."""
         self._keep = []
         kk = _f64(k)
         rad, at, pot = self._radial(system), self._atoms(system), self._potential(system)
-        sl, band = ctypes.c_int(), ctypes.c_int()
+        sl, band, rows = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         err = (ctypes.c_double * 4)()
-        ms = (ctypes.c_double * 5)()
+        ms = (ctypes.c_double * 10)()
         st = self._lib.flapw_tune(self._h, _ptr(kk), int(g.shape[0]), _dptr(g), ctypes.byref(at), ctypes.byref(rad),
                                   ctypes.byref(pot), PRECISIONS.get(prec, prec), float(tol), ctypes.byref(sl),
-                                  ctypes.byref(band), err, ms)
-        res = {"slices": sl.value, "band": band.value, "digit_err": list(err), "band_ms": list(ms)}
+                                  ctypes.byref(band), ctypes.byref(rows), err, ms)
+        res = {"slices": sl.value, "band": band.value, "stage_rows": rows.value, "digit_err": list(err),
+               "band_ms": list(ms)}
         if st != 0:
             e = FlapwError(st, self._lib.flapw_last_error(self._h).decode())
             e.result = res

@@ -206,7 +206,7 @@ def _call_tune(f, cell, tol, prec=3, n_g=None):
     err = (ctypes.c_double * 4)()
     st = f._lib.flapw_tune(f._h, F._ptr(k), cell.n_g(0) if n_g is None else n_g, ctypes.c_void_p(0x1000),
                            ctypes.byref(at), ctypes.byref(rad), ctypes.byref(pot), prec, tol, ctypes.byref(sl),
-                           ctypes.byref(band), err, None)
+                           ctypes.byref(band), None, err, None)
     return st, sl.value, band.value
 
 
@@ -325,6 +325,9 @@ def test_release_workspace(handle, lib):
     assert handle.workspace_bytes == 0
     handle.release_workspace()
     assert lib.flapw_release_workspace(None) == -1
+    assert lib.flapw_set_workspace_limit(None, 0) == -1
+    assert lib.flapw_set_workspace_limit(handle._h, 1 << 30) == 0
+    assert lib.flapw_set_workspace_limit(handle._h, -5) == 0
 
 
 def test_interstitial_validation(handle, lib):

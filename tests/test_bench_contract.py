@@ -35,7 +35,7 @@ def test_no_gpu_is_an_error():
 
 
 def test_source_hash_is_the_kernel_file_hash():
-    path = os.path.join(ROOT, "paper_1602_06589_amd", "csrc", "split_mod.hip")
+    path = os.path.join(ROOT, "paper_1602_06589_amd", "csrc", "mod_contract.hip")
     with open(path, "rb") as f:
         assert bench.kernel_sources_sha("i8mod") == hashlib.sha256(f.read()).hexdigest()[:16]
 

@@ -49,7 +49,8 @@ def _relfro(got, ref):
 
 
 def _bits(nm):
-    """Integer width B for nm moduli (pairwise coprime odd numbers, taken greedily from 255 down)."""
+    """Integer width B (rounded down) for nm moduli (pairwise coprime odd numbers, taken greedily from
+    255 down); the columns are scaled to a norm between 2^B and 2^(B+1)."""
     mods, c = [], 255
     while len(mods) < nm:
         if all(math.gcd(c, m) == 1 for m in mods):
@@ -129,8 +130,8 @@ def test_mod_contract_random_operands(ctx, oracle_lib):
 @pytest.mark.parametrize("nm", [8, 14])
 def test_mod_single_entry_columns(ctx, oracle_lib, nm):
     """Every column of P = [A; B] has one nonzero entry, so the column scaling turns it into an
-    integer within a factor 2 of 2^B: the largest magnitudes the residue step sees (B = 50 at 14
-    moduli), with mantissas up to 2 - 2^-40, signs and phases of all kinds, and magnitudes spread
+    integer within 2^-7 of 2^B: the largest magnitudes the residue step sees (B = 50 at 14 moduli),
+    with mantissas up to 2 - 2^-40, signs and phases of all kinds, and magnitudes spread
     over 2^-30..2^30 between columns.  A residue off by one modulus would come back from the
     reconstruction as an error of order M/p relative to the scaled product, far above the bound."""
     print(f"i8mod single-entry columns, {nm} moduli", flush=True)
@@ -200,3 +201,20 @@ def test_mod_c2_sampled(ctx, oracle_lib):
     """The 256-atom precision workload (l_max 10, l'' 8, N = 6000) on sampled entries."""
     errs = _sampled(ctx, oracle_lib, synthcells.config(2), nsamp=40)
     assert max(errs) < TOL_SPLIT, errs
+
+
+def test_mod_stage_depths_agree(ctx):
+    """The contraction kernel with 32-row LDS stages (four ring buffers) returns the same H and S,
+    bit for bit, as with 64-row stages (three buffers): the sums modulo each p are exact either way."""
+    import os
+    cell = _mixed(seed=19, n_g=421, n_k=2)
+    g = [_dev(x) for x in cell.gvecs]
+    ref = [(H.cpu().numpy(), S.cpu().numpy()) for H, S in ctx.hs_generate(cell, cell.kpts, g, prec="i8mod")]
+    os.environ["FLAPW_MOD_STAGE_ROWS"] = "32"
+    try:
+        got = [(H.cpu().numpy(), S.cpu().numpy()) for H, S in ctx.hs_generate(cell, cell.kpts, g, prec="i8mod")]
+    finally:
+        del os.environ["FLAPW_MOD_STAGE_ROWS"]
+    for ik, ((a, b), (c, d)) in enumerate(zip(ref, got)):
+        up = np.triu(np.ones((cell.n_g(ik), cell.n_g(ik)), bool)).T
+        assert np.array_equal(a[up], c[up]) and np.array_equal(b[up], d[up]), ik
