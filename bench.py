@@ -268,6 +268,40 @@ def operand_study(config: int, slices: int, reps: int = 2):
     return res
 
 
+def oracle_times(configs, one_core_max_n: int = 300, full_max_n: int = 3000, nsamp: int = 384):
+    """The oracle's time per k-point for the named workloads, on the host cores: whole k-points
+    (H and S of every basis-function pair, T, coefficients) up to full_max_n basis functions, and on
+    one core (OMP_NUM_THREADS=1, a child process) up to one_core_max_n; larger k-points are
+    extrapolated from a random principal submatrix as in the CPU baseline and labelled so."""
+    import subprocess
+    import synthcells
+    import oracle
+    oracle._load()
+    out = []
+    for c in configs:
+        cell = synthcells.config(c, n_k=1)
+        n = cell.n_g(0)
+        rec = {"workload": cell.name, "n_g": n, "K": cell.k_rows(), "cores": oracle_threads()}
+        if n <= full_max_n:
+            t0 = time.perf_counter()
+            oracle.hs_full(cell, 0)
+            rec["seconds_full"] = time.perf_counter() - t0
+        else:
+            base, _ = cpu_baseline_leg(cell, sample_indices(n, nsamp))
+            rec["seconds_extrapolated"] = base["seconds_per_kpoint_extrapolated"]
+            rec["extrapolation"] = base["extrapolation"]
+        if n <= one_core_max_n:
+            code = (f"import sys, time; sys.path.insert(0, {ROOT!r}); import synthcells, oracle; "
+                    f"cell = synthcells.config({c}, n_k=1); t0 = time.perf_counter(); oracle.hs_full(cell, 0); "
+                    "print(time.perf_counter() - t0)")
+            env = dict(os.environ, OMP_NUM_THREADS="1")
+            r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=3600)
+            rec["seconds_full_one_core"] = float(r.stdout.strip().splitlines()[-1])
+        print(f"# oracle {json.dumps(rec)}", flush=True)
+        out.append(rec)
+    return out
+
+
 def make_parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +335,10 @@ def make_parser() -> argparse.ArgumentParser:
                     help="mesh points of the radial-setup leg (radial functions and integrals of the "
                          "workload's atom types); 0 skips the leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-times", action="store_true",
+                    help="only time the CPU oracle per k-point on the named workloads 0-4 (whole k-points where "
+                         "that takes minutes at most, else extrapolated from a sample; one core on the smallest) "
+                         "and exit")
     ap.add_argument("--operand-study", action="store_true",
                     help="only time the modular contraction of one k-point-sized problem on random and on constant "
                          "operands (same instructions, different switching activity) and exit")
@@ -319,6 +357,9 @@ def main():
         return
     if args.operand_study:
         print(json.dumps(operand_study(args.config, args.slices or 11)))
+        return
+    if args.oracle_times:
+        print(json.dumps(oracle_times(range(5))))
         return
     if args.copy_calib:
         import torch
