@@ -302,6 +302,35 @@ def oracle_times(configs, one_core_max_n: int = 300, full_max_n: int = 3000, nsa
     return out
 
 
+def eigen_leg(config: int, prec: str, vectors: bool = True):
+    """The generalized eigensolve of k-point 0 (full H and S: muffin tins plus the interstitial
+    region with v_int = 0.1): generation time, flapw_eigensolve time (HIP events on the stream),
+    and the lowest and highest eigenvalues."""
+    import torch
+    import synthcells
+    from paper_1602_06589_amd import Flapw
+    cell = synthcells.config_separated(config, n_k=1)
+    g = [torch.as_tensor(np.ascontiguousarray(cell.gvecs[0]), device="cuda")]
+    stream = torch.cuda.current_stream()
+    res = {"workload": cell.name, "n_g": cell.n_g(0), "prec": prec, "vectors": vectors}
+    with Flapw() as fl:
+        fl.set_interstitial(True, cell.lattice, 0.1)
+        (H, S), = fl.hs_generate(cell, cell.kpts, g, prec=prec)        # warm-up (allocations, tuning-free)
+        for name, fn in (("generate", lambda: fl.hs_generate(cell, cell.kpts, g, prec=prec, out=[(H, S)])),
+                         ("eigensolve", lambda: fl.eigensolve(H, S, vectors=vectors))):
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            out = fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            res[name + "_ms"] = a.elapsed_time(b)
+        w = out[0].cpu().numpy()
+        res.update({"eps_min": float(w[0]), "eps_max": float(w[-1])})
+    print(f"# eigen {json.dumps(res)}", flush=True)
+    return res
+
+
 def make_parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,6 +364,9 @@ def make_parser() -> argparse.ArgumentParser:
                     help="mesh points of the radial-setup leg (radial functions and integrals of the "
                          "workload's atom types); 0 skips the leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eigen", action="store_true",
+                    help="only time the generation with the interstitial terms and the generalized eigensolve "
+                         "H c = eps S c of k-point 0 of --config (precision: the first of --precs) and exit")
     ap.add_argument("--oracle-times", action="store_true",
                     help="only time the CPU oracle per k-point on the named workloads 0-4 (whole k-points where "
                          "that takes minutes at most, else extrapolated from a sample; one core on the smallest) "
@@ -360,6 +392,9 @@ def main():
         return
     if args.oracle_times:
         print(json.dumps(oracle_times(range(5))))
+        return
+    if args.eigen:
+        print(json.dumps(eigen_leg(args.config, args.precs.split(",")[0].partition("+")[0])))
         return
     if args.copy_calib:
         import torch

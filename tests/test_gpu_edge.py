@@ -41,6 +41,14 @@ def _relfro(got, ref):
     return float(np.linalg.norm(got - ref) / den) if den > 0 else float(np.linalg.norm(got))
 
 
+def _rel_err(got, ref):
+    """The larger of the relative Frobenius error and the largest entry error relative to the
+    largest entry: a bound on either alone would let the other slip."""
+    e = float(np.abs(got - ref).max() / np.abs(ref).max()) if np.abs(ref).max() > 0 else float(np.abs(got).max())
+    return max(_relfro(got, ref), e)
+
+
+
 def _cell(n_g, types=(0, 1, 0), lmax=(4, 6), lpot=4, seed=3, a=9.0):
     rng = np.random.default_rng(seed)
     pos = rng.uniform(0, a, size=(len(types), 3))
@@ -53,8 +61,8 @@ def _check_full(handles, oracle_lib, cell, prec, method):
     out = handles[method].hs_generate(cell, cell.kpts, [_dev(g) for g in cell.gvecs], prec=prec)
     for ik, (H, S) in enumerate(out):
         Ho, So = oracle_lib.hs_full(cell, ik)
-        eh = _relfro(_upper(H.cpu().numpy()), Ho)
-        es = _relfro(_upper(S.cpu().numpy()), So)
+        eh = _rel_err(_upper(H.cpu().numpy()), Ho)
+        es = _rel_err(_upper(S.cpu().numpy()), So)
         tol_s = 1e-12 if method == "legendre" else TOL[prec]
         assert eh < TOL[prec] and es < tol_s, (prec, method, ik, eh, es)
         assert np.all(np.diag(H.cpu().numpy()).imag == 0.0) and np.all(np.diag(S.cpu().numpy()).imag == 0.0)
