@@ -47,9 +47,10 @@ sys.path.insert(0, ROOT)
 PEAKS = {"fp64": 78.6, "bf16": 2500.0, "i8": 5000.0, "i8mod": 5000.0}   # MI355X dense matrix-core peaks, T(FL)OP/s
 # int8 (or bf16) operations the split kernel executes per algorithmic FP64 flop: 8 ops per complex
 # multiply-add per digit pair (4 real products), s(s+1)/2 pairs, against 8 flops per complex
-# multiply-add in the FP64 count; the modular path runs one product per modulus
+# multiply-add in the FP64 count; the modular path splits each complex product modulo a modulus
+# into two real ones (4 ops per complex multiply-add)
 def executed_per_flop(slices: int, prec: str = "i8") -> float:
-    return float(slices) if prec == "i8mod" else slices * (slices + 1) / 2.0
+    return slices / 2.0 if prec == "i8mod" else slices * (slices + 1) / 2.0
 KERNEL = {"fp64": "hs_fp64", "bf16": "hs_split", "i8": "hs_split", "i8mod": "hs_mod"}
 DEFAULT_SLICES = {"i8": 6, "bf16": 6, "i8mod": 11}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")

@@ -75,14 +75,16 @@ typedef enum {
  *               so every call with it returns FLAPW_ERR_UNSUPPORTED.
  *   SPLIT_I8    the BF16 scheme with int8 digits (first in [-127, 127], later in [-64, 64]) and
  *               exact int32 accumulation over 4096 rows.  3..6 digits.
- *   SPLIT_I8_MOD  modular split: each operand column is scaled by a power of two so that its
- *               2-norm is below 2^B and rounded to integers; the exact integer products are
- *               computed modulo `slices` pairwise coprime odd moduli <= 255 (one int8 matrix-core
- *               product per modulus, int32 accumulation) and rebuilt by the Chinese remainder
- *               theorem in FP64 (B = min(50, floor((log2 M - 1)/2)), M the product of the
- *               moduli).  8..14 moduli.  Needs, per k-point in flight, 2 `slices` bytes per
- *               element of each of three 2K x N operands plus 64 `slices` KiB per 128 x 128
- *               output tile of S and of H.
+ *   SPLIT_I8_MOD  modular split: each operand column is scaled (by 2^B over its 2-norm, to 8
+ *               significant bits) and rounded to integers; the exact integer products are
+ *               computed modulo `slices` pairwise coprime odd moduli <= 255 in which -1 is a
+ *               square (241, 233, 229, 221, 205, 197, 193, 181, 173, 157, 149, 137, 113, 109, in
+ *               this order), each complex product as two real int8 matrix-core products with
+ *               int32 accumulation, and rebuilt by the Chinese remainder theorem in FP64
+ *               (B = min(50, (log2 M - 1)/2 - 0.001), M the product of the moduli).  8..14
+ *               moduli.  Needs, per k-point in flight, 2 `slices` bytes per element of each of
+ *               three 2K x N operands plus 64 `slices` KiB per 128 x 128 output tile of S and of
+ *               H.
  * `slices` (the digit or modulus count) outside the ranges above returns FLAPW_ERR_UNSUPPORTED
  * (FLAPW_ERR_ARG beyond FLAPW_SLICES_CAP digits or FLAPW_MODULI_CAP moduli, or below 0); 0
  * selects the count flapw_tune chose for the same precision and problem shape, else the default

@@ -163,7 +163,9 @@ hipError_t launch_interstitial(const double *g, const double kvec[3], const doub
 
 // Modular split precision (split_mod.hip).  Moduli p_m, 1/p_m as double-double, the CRT
 // constants w_m = (M/p_m)^-1 mod p_m, M = prod p_m as double-double, and the integer range: the
-// column norm 2^B the operands are scaled to (bits_real = B, bits = floor(B), two2b = 2^B).
+// column norm 2^B the operands are scaled to (bits_real = B, bits = floor(B), two2b = 2^B).  Per
+// modulus also a square root j_m of -1 and the inverses of 2 and of 2 j_m (all in the symmetric
+// range), which split the complex products mod p_m into two real ones.
 constexpr int kModCap = 14;
 constexpr int kModMin = 8;
 constexpr int kModTile = 128;   // output tile edge of the modular contraction
@@ -177,6 +179,9 @@ struct ModTable {
     double two2b;
     int p[kModCap];
     int w[kModCap];
+    int jr[kModCap];
+    int h2[kModCap];
+    int h2j[kModCap];
     double inv_p[kModCap];
     double inv_p_lo[kModCap];
     double M_hi, M_lo;

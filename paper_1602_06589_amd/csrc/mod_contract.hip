@@ -1,20 +1,20 @@
 // Modular split precision: the contraction modulo each modulus (the scheme, the residue slicing
 // and the reconstruction are described in split_mod.hip).
 //
-// Residues.  r = X' mod p_m in the symmetric range [-(p-1)/2, (p-1)/2] fits int8; the moduli are
-// odd so that -128 never occurs and the packed byte negation below never carries into the next
-// byte.  Per modulus the product conj(X)^T Y runs on v_mfma_i32_32x32x32_i8 over 32-row groups, the
-// real and the imaginary parts of a group in separate 1 KB fragments (lanes 0-31 rows 0-15, lanes
-// 32-63 rows 16-31): Re = Xr^T Yr + Xi^T Yi and Im = Xr^T Yi + (-Xi)^T Yr, four products per group
-// and pair of 32 x 32 tiles, from four fragment reads per tile row and column and one negated
-// fragment.  A complex row adds at most 2 * 127^2 to an int32 accumulator; accumulators are reduced
-// mod p every kFlushStages stages (32768 rows), so they stay below 2^31.
+// Residues.  r = X' mod p_m in the symmetric range [-(p-1)/2, (p-1)/2] fits int8.  Each operand is
+// stored as the residues of its two evaluations at the square roots +-j of -1 mod p_m (the left one
+// conjugated), so that z1 = U1^T Y1 = Re + j Im and z2 = U2^T Y2 = Re - j Im are plain real products.
+// Per modulus they run on v_mfma_i32_32x32x32_i8 over 32-row groups, each evaluation of a group in a
+// 1 KB fragment (lanes 0-31 rows 0-15, lanes 32-63 rows 16-31): two products per group and pair of
+// 32 x 32 tiles, from two fragment reads per tile row and column.  A row adds at most 127^2 to an
+// int32 accumulator; accumulators are reduced mod p every kFlushStages stages (65536 rows), so they
+// stay below 2^31.  The epilogue turns z1, z2 into Re = (z1 + z2) / 2 and Im = (z1 - z2) / (2 j).
 //
 //   hs_mod_i8_kernel<CH> one block per (256 x 128 output block, modulus): eight waves of 64 x 64,
 //                       stages of 16 CH rows copied to LDS by global_load_lds into a ring of three
 //                       (CH = 4) or four (CH = 2) buffers, the younger stages in flight; fragments
-//                       of the next 16-row chunk read ahead of the MFMAs; writes the residues (int8,
-//                       32 KB per 128 x 128 tile) to the problem's scratch
+//                       of the next 32-row group read ahead of the MFMAs; writes the residues of Re
+//                       and Im (int8, 32 KB per 128 x 128 tile) to the problem's scratch
 #include "context.hpp"
 
 namespace flapw {
@@ -36,7 +36,7 @@ struct ModStage {
                                                          // use the gfx9 encoding: vmcnt bits 3:0, expcnt 6:4,
                                                          // lgkmcnt 11:8)
     static constexpr int kCopies = 12 * CH / 8;          // 1 KB copies per wave per stage
-    static constexpr int kFlushStages = 32768 / kStageRows;  // 32768 rows * 2 * 127^2 < 2^31
+    static constexpr int kFlushStages = 65536 / kStageRows;  // 65536 rows * 127^2 < 2^31
     static_assert(CH % 2 == 0 && kRing >= 2 && kRing <= 4 && (kRing - 2) * kCopies < 16, "stage ring");
     static_assert(kRing * kStageBytes <= 163840, "LDS budget");
 };
@@ -48,13 +48,6 @@ __device__ inline int mod_step(int x, int p, float ipf)
 {
     const int q = (int)rintf((float)x * ipf);
     return x - q * p;
-}
-
-// Two's-complement negation of each of the four bytes of x; exact for bytes in [-127, 127] (the
-// residues of odd moduli), where no carry leaves a byte.
-__device__ __forceinline__ int neg_bytes(int x)
-{
-    return (int)((((unsigned)x ^ 0x7f7f7f7fu) + 0x01010101u) ^ 0x80808080u);
 }
 
 // Work-group barrier of the stage ring.  Before it, the wave waits until at most `in_flight`
@@ -148,68 +141,51 @@ __global__ __launch_bounds__(512, 1) void hs_mod_i8_kernel(const ModProblemDev *
             // slot of stage st + kRing - 1, the one read last at stage st - 1
             const int bn = b == 0 ? kRing - 1 : b - 1;
             if (st + kRing - 1 < nst) MOD_COPY(st + kRing - 1, bn);
-            // fragments of 32-row group g: real parts at +2048 g, imaginary parts at +2048 g + 1024;
-            // lane (half, col) holds rows 16 half .. 16 half + 15 of column col
+            // fragments of 32-row group g: evaluations at j at +2048 g, at -j at +2048 g + 1024; lane
+            // (half, col) holds rows 16 half .. 16 half + 15 of column col
             const unsigned char *stage = smem + b * kStageBytes;
             const unsigned char *la = stage + (2 * wm) * kRunBytes + half * 512 + col * 16;
             const unsigned char *lb = stage + (8 + 2 * wn) * kRunBytes + half * 512 + col * 16;
-            v4i ar[2], ai[2], br[2], bi[2];
+            v4i a1[2], a2[2], b1[2], b2[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                ar[i] = *reinterpret_cast<const v4i *>(la + i * kRunBytes);
-                ai[i] = *reinterpret_cast<const v4i *>(la + i * kRunBytes + 1024);
-                br[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes);
-                bi[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes + 1024);
+                a1[i] = *reinterpret_cast<const v4i *>(la + i * kRunBytes);
+                a2[i] = *reinterpret_cast<const v4i *>(la + i * kRunBytes + 1024);
+                b1[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes);
+                b2[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes + 1024);
             }
 #pragma unroll
             for (int gg = 0; gg < kGroups; ++gg) {
-                v4i nar[2], nai[2], nbr[2], nbi[2];
+                v4i na1[2], na2[2], nb1[2], nb2[2];
                 if (gg + 1 < kGroups) {          // next group's fragments, read ahead
                     const int o = (gg + 1) * 2048;
 #pragma unroll
                     for (int i = 0; i < 2; ++i) {
-                        nar[i] = *reinterpret_cast<const v4i *>(la + i * kRunBytes + o);
-                        nai[i] = *reinterpret_cast<const v4i *>(la + i * kRunBytes + o + 1024);
-                        nbr[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes + o);
-                        nbi[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes + o + 1024);
+                        na1[i] = *reinterpret_cast<const v4i *>(la + i * kRunBytes + o);
+                        na2[i] = *reinterpret_cast<const v4i *>(la + i * kRunBytes + o + 1024);
+                        nb1[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes + o);
+                        nb2[i] = *reinterpret_cast<const v4i *>(lb + i * kRunBytes + o + 1024);
                     }
                 }
                 // keep the reads ahead of this group's products (the scheduler would sink them)
                 __builtin_amdgcn_sched_barrier(0);
-                // Re conj(X) Y = Xr Yr + Xi Yi, Im = Xr Yi - Xi Yr; each accumulator's two products are
-                // seven MFMAs apart
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
-                        acc[i][j][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[i], br[j], acc[i][j][0], 0, 0, 0);
+                        acc[i][j][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1[i], b1[j], acc[i][j][0], 0, 0, 0);
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
-                        acc[i][j][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[i], bi[j], acc[i][j][1], 0, 0, 0);
-                v4i an[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) an[i][q] = neg_bytes(ai[i][q]);
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ai[i], bi[j], acc[i][j][0], 0, 0, 0);
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(an[i], br[j], acc[i][j][1], 0, 0, 0);
+                        acc[i][j][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2[i], b2[j], acc[i][j][1], 0, 0, 0);
                 if (gg + 1 < kGroups) {
 #pragma unroll
                     for (int i = 0; i < 2; ++i) {
-                        ar[i] = nar[i];
-                        ai[i] = nai[i];
-                        br[i] = nbr[i];
-                        bi[i] = nbi[i];
+                        a1[i] = na1[i];
+                        a2[i] = na2[i];
+                        b1[i] = nb1[i];
+                        b2[i] = nb2[i];
                     }
                 }
             }
@@ -235,6 +211,19 @@ __global__ __launch_bounds__(512, 1) void hs_mod_i8_kernel(const ModProblemDev *
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][c][r] = mod_step(acc[i][j][c][r], pi, ipf);
 #undef MOD_COPY
+    // Re = (z1 + z2) / 2, Im = (z1 - z2) / (2 j) mod p (|z1 +- z2| <= p - 1, inverses in the
+    // symmetric range: the products stay below 2^15)
+    const int h2 = mt.h2[mo], h2j = mt.h2j[mo];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int z1 = acc[i][j][0][r], z2 = acc[i][j][1][r];
+                acc[i][j][0][r] = mod_step(mod_step((z1 + z2) * h2, pi, ipf), pi, ipf);
+                acc[i][j][1][r] = mod_step(mod_step((z1 - z2) * h2j, pi, ipf), pi, ipf);
+            }
 
     // residues of the wave's 64 x 64 block, stored per 128 x 128 tile (2I + (wm >> 1), J) as
     // [wave in tile][i][j][re, im][lane][16 bytes]; tiles below the diagonal are skipped

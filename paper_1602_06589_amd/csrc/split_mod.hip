@@ -10,14 +10,26 @@
 // |X'| <= 2^B <= 2^50 (exact in FP64).  B is real:
 // B = min(50, (log2 M - 1)/2 - 0.001), M = prod p_m.  By Cauchy-Schwarz every exact integer
 // product entry C'_ij = Re or Im of sum_k conj(X'_ki) Y'_kj has |C'| <= ||X'_i|| ||Y'_j||, and the
-// rounding adds at most sqrt(2K)/2 < 2^15 to a column norm of 2^B, B > 31 (a factor below
-// 1 + 2^-16), against the 2^-0.002 margin in 2^(2B) <= M/2: |C'| < M/2 and C' is the unique residue
+// rounding adds at most sqrt(2K)/2 < 2^15 to a column norm of 2^B, B > 30 (a factor below
+// 1 + 2^-15), against the 2^-0.002 margin in 2^(2B) <= M/2: |C'| < M/2 and C' is the unique residue
 // of C' mod M in (-M/2, M/2).  Scaling each column to the largest admissible norm (instead of a
 // power of two, which leaves it anywhere in [2^(B-1), 2^B)) makes the rounding error, relative to the
 // column, the smallest the range allows: about 1.47 times smaller in the mean square.
 //
 // Residues.  r = X' mod p_m in the symmetric range [-(p-1)/2, (p-1)/2] fits int8 (the moduli are
 // odd, so -128 never occurs); the products modulo each p_m run in mod_contract.hip.
+//
+// Complex products as two real ones.  Every modulus has a square root j of -1 (j^2 = -1 mod p; for
+// odd p this holds exactly when every prime factor of p is 1 mod 4).  Then the Gaussian integers mod
+// p split into two copies of the integers mod p: x = xr + i xi goes to the pair of evaluations
+// (xr + j xi, xr - j xi) mod p, and sums and products go to the pairs' componentwise sums and
+// products.  conj(x) goes to (xr - j xi, xr + j xi), so z = conj(X)^T Y goes to
+// z1 = (Xr - j Xi)^T (Yr + j Yi) = Re z + j Im z and z2 = (Xr + j Xi)^T (Yr - j Yi) = Re z - j Im z,
+// two real products, and Re z = (z1 + z2) / 2, Im z = (z1 - z2) / (2 j) mod p.  Against the four
+// real products of Re and Im this halves the matrix-core work per modulus; the price is that the
+// admissible moduli are smaller (14 of them <= 255, from 241 down to 109), so a given range M takes
+// about one modulus more.  Each operand is stored as the residues of its two evaluations, in the
+// places of the real and the imaginary part.
 //
 // Reconstruction.  With w_m = (M/p_m)^(-1) mod p_m, C'/M = sum_m y_m / p_m (mod 1) for the
 // residues c_m and y_m = c_m w_m mod p_m; the sum is formed in double-double from 1/p_m = hi + lo,
@@ -28,8 +40,8 @@
 //   mod_colnorm_kernel  per column: s_c of P, of d.P (right operand of S) and of Q (right of H)
 //   mod_colsum_kernel   the same s_c from column-sum shares written by the real-T panel kernel
 //   mod_slice_kernel    residues of all moduli, stored as [modulus][32-column block][32-row group]
-//                       [re, im][16-row half][32 columns][16 bytes] (one 1 KB MFMA fragment per
-//                       part and group)
+//                       [evaluation at j, at -j][16-row half][32 columns][16 bytes] (one 1 KB MFMA
+//                       fragment per evaluation and group)
 //   hs_mod_i8_kernel    (mod_contract.hip) the products modulo each p_m
 //   mod_crt_kernel      one block per tile: reads the residues of all moduli, rebuilds and
 //                       scales the FP64 values, writes the upper triangle of S or H
@@ -122,28 +134,45 @@ __global__ __launch_bounds__(256) void mod_colsum_kernel(const double *__restric
     sRH[c] = mod_scale(sq, two2b);
 }
 
-// residues of 16 integer-valued doubles for every modulus, 16 bytes per modulus at out + m * mstride
-__device__ inline void write_residues(const double (&v)[16], const ModTable &mt, int8_t *out, long long mstride)
+// a mod p in [-(p-1)/2, (p-1)/2] for odd p and |a| <= h + h^2, h = (p-1)/2: a/p lies at least
+// 1/(2p) >= 2^-9 from a half-integer and the float quotient is off by at most |a/p| 2^-23 < 2^-16.
+__device__ inline int sym_mod_small(int a, int p, float ipf)
+{
+    return a - (int)rintf((float)a * ipf) * p;
+}
+
+// Residues of 16 Gaussian integers xr + i xi (integer-valued doubles) for every modulus, as the
+// evaluations xr + sg j xi (16 bytes at out0 + m mstride) and xr - sg j xi (at out1 + m mstride);
+// sg = -1 stores the conjugate.
+__device__ inline void write_residues(const double (&xr)[16], const double (&xi)[16], int sg, const ModTable &mt,
+                                      int8_t *out0, int8_t *out1, long long mstride)
 {
     for (int m = 0; m < mt.nm; ++m) {
         const double p = (double)mt.p[m], ip = mt.inv_p[m];
-        unsigned w[4];
+        const int pm = mt.p[m], js = sg * mt.jr[m];
+        const float ipf = (float)ip;
+        unsigned w0[4], w1[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            unsigned packed = 0;
+            unsigned u0 = 0, u1 = 0;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) packed |= ((unsigned)sym_mod(v[4 * q + b], p, ip) & 0xffu) << (8 * b);
-            w[q] = packed;
+            for (int b = 0; b < 4; ++b) {
+                const int a = sym_mod(xr[4 * q + b], p, ip), c = sym_mod(xi[4 * q + b], p, ip);
+                u0 |= ((unsigned)sym_mod_small(a + js * c, pm, ipf) & 0xffu) << (8 * b);
+                u1 |= ((unsigned)sym_mod_small(a - js * c, pm, ipf) & 0xffu) << (8 * b);
+            }
+            w0[q] = u0;
+            w1[q] = u1;
         }
-        *reinterpret_cast<uint4 *>(out + m * mstride) = make_uint4(w[0], w[1], w[2], w[3]);
+        *reinterpret_cast<uint4 *>(out0 + m * mstride) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+        *reinterpret_cast<uint4 *>(out1 + m * mstride) = make_uint4(w1[0], w1[1], w1[2], w1[3]);
     }
 }
 
 // grid (npm/32, kp2/128): thread (m = tid % 32, chunk = tid / 32) handles 16 rows of column
-// 32 blockIdx.x + m.  MODE 0: residues of P (left) and d.P (right of S); MODE 1: of Q (right of H);
-// MODE 2: of P alone (S is not contracted).  The 16 values are read once and each operand (its real
-// parts, then its imaginary parts) is formed and reduced in turn, so that one operand's 16 integers
-// are live beside them.
+// 32 blockIdx.x + m.  MODE 0: residues of P (left, conjugated) and d.P (right of S); MODE 1: of Q
+// (right of H); MODE 2: of P alone (S is not contracted).  The 16 values are read once and each
+// operand is formed and reduced in turn, so that one operand's 32 integers are live beside them.
 template <int MODE>
 __global__ __launch_bounds__(256) void mod_slice_kernel(const double2 *__restrict__ P, const double2 *__restrict__ Q,
                                                         const double *__restrict__ d, long long ld, int kp2, int np,
@@ -157,52 +186,42 @@ __global__ __launch_bounds__(256) void mod_slice_kernel(const double2 *__restric
     const long long ch = (long long)blockIdx.y * 8 + (threadIdx.x >> 5);
     const long long nch = kp2 / 16, ncb = gridDim.x;
     const long long mstride = ncb * nch * 1024;
-    // 32-row group ch / 2: real parts in its first 1 KB fragment, imaginary parts in the second;
+    // 32-row group ch / 2: the evaluations at j in its first 1 KB fragment, at -j in the second;
     // this 16-row chunk is half ch % 2 of each
     const long long off = (cb * nch + (ch & ~1LL)) * 1024 + (ch & 1) * 512 + m * 16, offi = off + 1024;
     const long long r0 = ch * 16;
-    double xr[16];
-    if (MODE == 2) {
-        const double sc = sL[col];
-        double2 v[16];
+    const double2 *src = MODE == 1 ? Q : P;
+    double2 v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = col < np ? P[col * ld + r0 + r] : make_double2(0.0, 0.0);
+    for (int r = 0; r < 16; ++r) v[r] = col < np ? src[col * ld + r0 + r] : make_double2(0.0, 0.0);
+    double xr[16], xi[16];
+    if (MODE != 1) {
+        const double s1 = sL[col];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) xr[r] = rint(v[r].x * sc);
-        write_residues(xr, mt, L + off, mstride);
+        for (int r = 0; r < 16; ++r) {
+            xr[r] = rint(v[r].x * s1);
+            xi[r] = rint(v[r].y * s1);
+        }
+        write_residues(xr, xi, -1, mt, L + off, L + offi, mstride);
+    }
+    if (MODE == 0) {
+        const double s2 = sRS[col];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) xr[r] = rint(v[r].y * sc);
-        write_residues(xr, mt, L + offi, mstride);
-    } else if (MODE == 0) {
-        // P is read once; the four operands (Re P, Im P, Re d.P, Im d.P) are formed and reduced one
-        // at a time, so only the 16 values of P and one operand are live
-        const double s1 = sL[col], s2 = sRS[col];
-        double2 v[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = col < np ? P[col * ld + r0 + r] : make_double2(0.0, 0.0);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) xr[r] = rint(v[r].x * s1);
-        write_residues(xr, mt, L + off, mstride);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) xr[r] = rint(v[r].y * s1);
-        write_residues(xr, mt, L + offi, mstride);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) xr[r] = rint(v[r].x * d[r0 + r] * s2);
-        write_residues(xr, mt, RS + off, mstride);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) xr[r] = rint(v[r].y * d[r0 + r] * s2);
-        write_residues(xr, mt, RS + offi, mstride);
-    } else {
+        for (int r = 0; r < 16; ++r) {
+            const double w = d[r0 + r];
+            xr[r] = rint(v[r].x * w * s2);
+            xi[r] = rint(v[r].y * w * s2);
+        }
+        write_residues(xr, xi, 1, mt, RS + off, RS + offi, mstride);
+    }
+    if (MODE == 1) {
         const double sc = sRH[col];
-        double2 v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = col < np ? Q[col * ld + r0 + r] : make_double2(0.0, 0.0);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) xr[r] = rint(v[r].x * sc);
-        write_residues(xr, mt, RH + off, mstride);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) xr[r] = rint(v[r].y * sc);
-        write_residues(xr, mt, RH + offi, mstride);
+        for (int r = 0; r < 16; ++r) {
+            xr[r] = rint(v[r].x * sc);
+            xi[r] = rint(v[r].y * sc);
+        }
+        write_residues(xr, xi, 1, mt, RH + off, RH + offi, mstride);
     }
 }
 
@@ -334,18 +353,45 @@ hipError_t launch_mod_crt(const ModProblemDev *probs, const TileDev *tiles, int 
     return hipGetLastError();
 }
 
-// Moduli: the pairwise coprime odd integers taken greedily from 255 downwards; B from M.
+// The smallest x > 0 with x^2 = -1 mod c, or 0 when -1 is not a square mod c.
+static int sqrt_minus_one(int c)
+{
+    for (int x = 1; x < c; ++x)
+        if ((x * x + 1) % c == 0) return x;
+    return 0;
+}
+
+// a mod p in [-(p-1)/2, (p-1)/2]
+static int sym_rep(long long a, int p)
+{
+    long long r = ((a % p) + p) % p;
+    return (int)(r > p / 2 ? r - p : r);
+}
+
+// inverse of a mod p (gcd(a, p) = 1), in [0, p)
+static long long inv_mod(long long a, long long p)
+{
+    long long r0 = p, r1 = ((a % p) + p) % p, s0 = 0, s1 = 1;
+    while (r1) {
+        const long long f = r0 / r1, r2 = r0 - f * r1, s2 = s0 - f * s1;
+        r0 = r1; r1 = r2; s0 = s1; s1 = s2;
+    }
+    return ((s0 % p) + p) % p;
+}
+
+// Moduli: the pairwise coprime odd integers <= 255 in which -1 is a square, taken greedily from 255
+// downwards (241, 233, 229, 221, 205, 197, 193, 181, 173, 157, 149, 137, 113, 109); B from M.
 ModTable make_mod_table(int nm)
 {
     ModTable t{};
     t.nm = nm;
     int c = 255, k = 0;
-    while (k < nm) {
-        bool ok = true;
-        for (int j = 0; j < k; ++j) {
+    while (k < nm && c > 1) {
+        bool ok = sqrt_minus_one(c) != 0;
+        for (int j = 0; ok && j < k; ++j) {
             int a = c, b = t.p[j];
             while (b) { const int r = a % b; a = b; b = r; }
-            if (a != 1) { ok = false; break; }
+            if (a != 1) ok = false;
         }
         if (ok) t.p[k++] = c;
         c -= 2;
@@ -365,12 +411,11 @@ ModTable make_mod_table(int nm)
         long long q = 1;                                   // (M / p) mod p
         for (int j = 0; j < nm; ++j)
             if (j != m) q = q * t.p[j] % p;
-        long long r0 = p, r1 = q, s0 = 0, s1 = 1;          // inverse of q mod p
-        while (r1) {
-            const long long f = r0 / r1, r2 = r0 - f * r1, s2 = s0 - f * s1;
-            r0 = r1; r1 = r2; s0 = s1; s1 = s2;
-        }
-        t.w[m] = (int)(((s0 % p) + p) % p);
+        t.w[m] = (int)inv_mod(q, p);
+        const int jr = sqrt_minus_one((int)p);
+        t.jr[m] = sym_rep(jr, (int)p);
+        t.h2[m] = sym_rep(inv_mod(2, p), (int)p);
+        t.h2j[m] = sym_rep(inv_mod(2LL * jr, p), (int)p);
         t.inv_p[m] = 1.0 / (double)p;
         t.inv_p_lo[m] = std::fma(-t.inv_p[m], (double)p, 1.0) / (double)p;
     }

@@ -1,5 +1,5 @@
-"""GPU parity of the modular split precision (residues modulo pairwise coprime moduli <= 256 on
-the int8 matrix cores, rebuilt by the Chinese remainder theorem) against the FP64 oracle.
+"""GPU parity of the modular split precision (residues modulo pairwise coprime moduli <= 255 on
+the int8 matrix cores, each complex product split into two real ones, rebuilt by the Chinese remainder theorem) against the FP64 oracle.
 
 Bar: relative Frobenius error <= 1e-10 per matrix (H and S separately) with the default 11
 moduli; the error falls with every extra modulus, within 2^(10-B) where B is the integer bit
@@ -56,12 +56,16 @@ def _rel_err(got, ref):
 
 
 
+def _has_sqrt_minus_one(c):
+    return any((x * x + 1) % c == 0 for x in range(1, c))
+
+
 def _bits(nm):
-    """Integer width B (rounded down) for nm moduli (pairwise coprime odd numbers, taken greedily from
-    255 down); the columns are scaled to a norm between 2^B and 2^(B+1)."""
+    """Integer width B (rounded down) for nm moduli (pairwise coprime odd numbers <= 255 in which -1
+    is a square, taken greedily from 255 down); the columns are scaled to a norm of about 2^B."""
     mods, c = [], 255
     while len(mods) < nm:
-        if all(math.gcd(c, m) == 1 for m in mods):
+        if _has_sqrt_minus_one(c) and all(math.gcd(c, m) == 1 for m in mods):
             mods.append(c)
         c -= 2
     return min(50, int(math.floor((sum(math.log2(m) for m in mods) - 1) / 2)))
