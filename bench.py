@@ -214,6 +214,28 @@ def mfma_ceiling():
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def copy_ceiling():
+    """L2 -> LDS copy rates (LDS-DMA and through registers), HBM -> LDS streaming and LDS read rates
+    of the microbenchmark built next to the library, or None when it is not built."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1602_06589_amd", "copy_rate")
+    if not os.path.exists(exe):
+        return None
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def mod_copy_bytes(n: int, kp2: int, nm: int) -> int:
+    """Bytes the modular contraction copies from L2 into LDS for one k-point: every 256 x 128 block
+    of the S and the H upper triangles (2I <= J over 128-column tiles, N padded to 256 columns), per
+    modulus, copies 24 KB per 32-row group (256 + 128 columns x 2 evaluations x 32 bytes)."""
+    nt = 2 * ((n + 255) // 256)
+    blocks = sum(nt - 2 * i for i in range(nt // 2))
+    return 2 * nm * blocks * (kp2 // 32) * 24576
+
+
 def step_plan(is_head: bool, steps: int, warmup: int):
     """(warm-up replays, timed replays, eager profiled steps) of a path: the headline takes the
     requested counts; every other path at most 1 warm-up and 3 timed replays, and one eager step
@@ -588,6 +610,16 @@ def main():
         roof.update({"executed_ops_per_flop": executed_per_flop(slices, head), "executed_achieved": ex,
                      "executed_frac": ex / PEAKS[head], "slices": slices})
     ceil = mfma_ceiling() if args.ceiling else None
+    copies = copy_ceiling() if args.ceiling and head == "i8mod" else None
+    if copies:
+        kp2 = -(-2 * cell.k_rows() // 256) * 256          # contraction rows, padded like the library's
+        cb = [mod_copy_bytes(cell.n_g(i), kp2, slices) for i in range(len(cell.kpts))]
+        rate = float(np.mean(cb)) / (roof["avg_launch_ms"] * 1e-3) / 1e12
+        roof["stage_copies"] = {
+            "bytes_per_launch": float(np.mean(cb)), "TBps": rate, "l2_lds_ceiling_TBps": copies["l2_lds_dma_tbs"],
+            "frac": rate / copies["l2_lds_dma_tbs"], "rates": copies,
+            "note": "L2 -> LDS bytes of the contraction's stage copies against the LDS-DMA rate from L2 of a "
+                    "copy-only loop with the same stage structure"}
     if ceil:
         key = {"i8": "i8_random_TOPs", "i8mod": "i8_random_TOPs", "bf16": "bf16_random_TFLOPs",
                "fp64": "f64_random_TFLOPs"}[head]

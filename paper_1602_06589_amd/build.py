@@ -18,6 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libflapw_hip.so")
 MFMA_RATE = os.path.join(HERE, "mfma_rate")                  # matrix-core ceiling microbenchmark
+COPY_RATE = os.path.join(HERE, "copy_rate")                  # L2 -> LDS copy and LDS read rates
 ARCH = "gfx950"
 
 
@@ -70,8 +71,13 @@ def build(verbose: bool = False) -> str:
                                                                           "-o", MFMA_RATE], capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for mfma_rate.hip:\n" + r.stdout + r.stderr)
+    src = os.path.join(HERE, "microbench", "copy_rate.hip")
+    r = subprocess.run([_hipcc()] + [f for f in FLAGS if f != "-fPIC"] + [src, "-o", COPY_RATE], capture_output=True,
+                       text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for copy_rate.hip:\n" + r.stdout + r.stderr)
     if verbose:
-        print("built", LIB, "and", MFMA_RATE)
+        print("built", LIB, MFMA_RATE, "and", COPY_RATE)
     return LIB
 
 

@@ -134,32 +134,27 @@ __global__ __launch_bounds__(256) void mod_colsum_kernel(const double *__restric
     sRH[c] = mod_scale(sq, two2b);
 }
 
-// a mod p in [-(p-1)/2, (p-1)/2] for odd p and |a| <= h + h^2, h = (p-1)/2: a/p lies at least
-// 1/(2p) >= 2^-9 from a half-integer and the float quotient is off by at most |a/p| 2^-23 < 2^-16.
-__device__ inline int sym_mod_small(int a, int p, float ipf)
-{
-    return a - (int)rintf((float)a * ipf) * p;
-}
-
-// Residues of 16 Gaussian integers xr + i xi (integer-valued doubles) for every modulus, as the
-// evaluations xr + sg j xi (16 bytes at out0 + m mstride) and xr - sg j xi (at out1 + m mstride);
-// sg = -1 stores the conjugate.
+// Residues of 16 Gaussian integers xr + i xi (integer-valued doubles, |xr|, |xi| <= 2^50 (1 + 2^-15))
+// for every modulus, as the evaluations xr + sg j xi (16 bytes at out0 + m mstride) and xr - sg j xi
+// (at out1 + m mstride); sg = -1 stores the conjugate.  xi is reduced first (c = xi mod p, exact in
+// FP64); xr +- sg j c then stays within 2^50 (1 + 2^-15) + 127^2 and is reduced like xr.
 __device__ inline void write_residues(const double (&xr)[16], const double (&xi)[16], int sg, const ModTable &mt,
                                       int8_t *out0, int8_t *out1, long long mstride)
 {
     for (int m = 0; m < mt.nm; ++m) {
         const double p = (double)mt.p[m], ip = mt.inv_p[m];
-        const int pm = mt.p[m], js = sg * mt.jr[m];
-        const float ipf = (float)ip;
+        const double js = (double)(sg * mt.jr[m]);
         unsigned w0[4], w1[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             unsigned u0 = 0, u1 = 0;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int a = sym_mod(xr[4 * q + b], p, ip), c = sym_mod(xi[4 * q + b], p, ip);
-                u0 |= ((unsigned)sym_mod_small(a + js * c, pm, ipf) & 0xffu) << (8 * b);
-                u1 |= ((unsigned)sym_mod_small(a - js * c, pm, ipf) & 0xffu) << (8 * b);
+                const double x = xi[4 * q + b];
+                const double c = fma(-rint(x * ip), p, x);             // xi mod p, exact
+                const double r = xr[4 * q + b];
+                u0 |= ((unsigned)sym_mod(fma(js, c, r), p, ip) & 0xffu) << (8 * b);
+                u1 |= ((unsigned)sym_mod(fma(-js, c, r), p, ip) & 0xffu) << (8 * b);
             }
             w0[q] = u0;
             w1[q] = u1;

@@ -101,3 +101,10 @@ def test_error_estimate_reweights_the_sample():
     full = lambda U: U + np.triu(U, 1).conj().T
     direct = np.linalg.norm(full(got) - ref) / np.linalg.norm(ref)
     assert abs(e2["full_relF_est"] - direct) < 1e-9 * direct
+
+
+def test_mod_copy_bytes_counts_the_blocks_of_both_triangles():
+    """N = 11621 pads to 92 tiles of 128 columns: 2162 blocks of 256 x 128 with 2I <= J per matrix,
+    each copying 24 KB per 32-row group for every modulus."""
+    assert bench.mod_copy_bytes(11621, 123904, 11) == 2 * 11 * 2162 * (123904 // 32) * 24576
+    assert bench.mod_copy_bytes(256, 256, 8) == 2 * 8 * 2 * 8 * 24576
