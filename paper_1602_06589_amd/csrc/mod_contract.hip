@@ -25,22 +25,25 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-// Stage geometry for CH 16-row chunks per LDS stage (CH = 4: 64-row stages, the default; CH = 2:
-// 32-row stages) and NW waves per block (8 waves of 64 x 64 or 4 waves of 128 x 64 of the 256 x 128
-// block).  A stage is 12 runs (8 left and 4 right 32-column blocks) of CH 1 KB segments.
-template <int CH, int NW>
+// Stage geometry for CH 16-row chunks per LDS stage (CH = 4: 64-row stages; CH = 2: 32-row
+// stages) and blocks of BR x 128 (BR = 256 or 384 rows; eight waves of BR/4 x 64).  A stage is
+// BR/32 left and 4 right 32-column runs of CH 1 KB segments.
+template <int CH, int BR>
 struct ModStage {
     static constexpr int kChunks = CH;                   // 16-row chunks per LDS stage
     static constexpr int kGroups = CH / 2;               // 32-row groups per LDS stage
     static constexpr int kStageRows = 16 * CH;           // complex rows per LDS stage
-    static constexpr int kRunBytes = CH * 1024;          // one 32-column block over one stage
-    static constexpr int kStageBytes = 12 * kRunBytes;   // 8 left + 4 right column blocks
-    static constexpr int kRing = CH == 4 ? 3 : 4;        // LDS stage buffers: 144 or 96 KB
-    static constexpr int kCopies = 12 * CH / NW;         // 1 KB copies per wave per stage
-    static constexpr int kWM = NW == 8 ? 2 : 4;          // 32-row tiles per wave
+    static constexpr int kLeftRuns = BR / 32;            // 32-column runs of the left operand
+    static constexpr int kRuns = kLeftRuns + 4;
+    static constexpr int kRunBytes = CH * 1024;          // one 32-column run over one stage
+    static constexpr int kStageBytes = kRuns * kRunBytes;
+    static constexpr int kRing = 163840 / kStageBytes < 4 ? 163840 / kStageBytes : 4;  // LDS stage buffers
+    static constexpr int kWaves = 8;
+    static constexpr int kCopies = kRuns * CH / kWaves;  // 1 KB copies per wave per stage
+    static constexpr int kWM = BR / 128;                 // 32-row tiles per wave
     static constexpr int kWN = 2;                        // 32-column tiles per wave
     static constexpr int kFlushStages = 65536 / kStageRows;  // 65536 rows * 127^2 < 2^31
-    static_assert(CH % 2 == 0 && kRing >= 2 && (12 * CH) % NW == 0, "stage geometry");
+    static_assert(CH % 2 == 0 && kRing >= 2 && (kRuns * CH) % kWaves == 0 && BR % 128 == 0, "stage geometry");
     static_assert((kRing - 1) * kCopies < 64, "vmcnt field");
     static_assert(kRing * kStageBytes <= 163840, "LDS budget");
 };
@@ -82,26 +85,28 @@ __device__ inline void ring_wait(int later)
     }
 }
 
-// grid (n_tiles, nm): block tile blockIdx.x of the launch's list -- rows 256 I .. 256 I + 255
-// (the 128-row tiles 2I and 2I + 1), columns 128 J .. 128 J + 127 -- and modulus blockIdx.y.
-// NW waves, wave w computing the kWM x kWN tiles of 32 x 32 at rows 32 kWM (w / 2), columns
+// grid (n_tiles, nm): block tile blockIdx.x of the launch's list -- rows BR I .. BR I + BR - 1
+// (the 128-row tiles (BR/128) I ..), columns 128 J .. 128 J + 127 -- and modulus blockIdx.y.
+// Eight waves, wave w computing the kWM x 2 tiles of 32 x 32 at rows 32 kWM (w / 2), columns
 // 64 (w % 2) of the block tile.
 //
-// Pipeline: the fragments of the next 32-row group are read from LDS while the current group's
-// MFMAs run, across stage boundaries too.  At the last group of stage st the wave waits for stage
-// st + 1 to land (its own copies, then the barrier for everyone's), reads the first fragments of
-// stage st + 1, issues the group's MFMAs and then refills the slot of stage st (every read of it
-// has returned before the barrier) with stage st + kRing.  The copies thus run kRing - 1 stages
-// ahead of the reads.
-template <int CH, int NW>
-__global__ __launch_bounds__(NW * 64, 1) void hs_mod_i8_kernel(const ModProblemDev *__restrict__ probs,
-                                                               const TileDev *__restrict__ tiles, ModTable mt)
+// Pipeline.  Each 32-row group issues the z1 products (first evaluations), then reads the first
+// evaluations of the next group into the same registers, issues the z2 products and reads the
+// second evaluations of the next group: the reads of one half run under the other half's
+// products, and one group's fragments are live at a time.  At the last group of stage st, between
+// its two halves, the wave waits for stage st + 1 to land (its own copies, then the barrier for
+// everyone's; every read of stage st has returned by then), and after the group's products it
+// refills the slot of stage st with stage st + kRing: the copies run kRing - 1 stages ahead of
+// the reads.
+template <int CH, int BR>
+__global__ __launch_bounds__(512, 1) void hs_mod_i8_kernel(const ModProblemDev *__restrict__ probs,
+                                                           const TileDev *__restrict__ tiles, ModTable mt)
 {
-    using G = ModStage<CH, NW>;
+    using G = ModStage<CH, BR>;
     constexpr int kChunks = G::kChunks, kGroups = G::kGroups, kStageRows = G::kStageRows;
-    constexpr int kRunBytes = G::kRunBytes, kStageBytes = G::kStageBytes;
+    constexpr int kRunBytes = G::kRunBytes, kStageBytes = G::kStageBytes, kLeftRuns = G::kLeftRuns;
     constexpr int kRing = G::kRing, kCopies = G::kCopies, kFlushStages = G::kFlushStages;
-    constexpr int WM = G::kWM, WN = G::kWN;
+    constexpr int WM = G::kWM, WN = G::kWN, NW = G::kWaves;
     extern __shared__ __align__(16) unsigned char smem[];
     const TileDev td = tiles[blockIdx.x];
     const ModProblemDev pb = probs[td.prob];
@@ -111,7 +116,7 @@ __global__ __launch_bounds__(NW * 64, 1) void hs_mod_i8_kernel(const ModProblemD
     const long long nch = pb.kp2 / 16;
     const long long mstride = (long long)pb.ncb * nch * 1024;
     const long long cbytes = nch * 1024;                          // one 32-column block, all rows
-    const int8_t *Lg = pb.L + mo * mstride + 8LL * td.ti * cbytes;
+    const int8_t *Lg = pb.L + mo * mstride + (long long)kLeftRuns * td.ti * cbytes;
     const int8_t *Rg = (mat ? pb.RH : pb.RS) + mo * mstride + 4LL * td.tj * cbytes;
     const int nst = pb.kp2 / kStageRows;
     const int pi = mt.p[mo];
@@ -128,13 +133,14 @@ __global__ __launch_bounds__(NW * 64, 1) void hs_mod_i8_kernel(const ModProblemD
                 for (int r = 0; r < 16; ++r) acc[i][j][c][r] = 0;
 
     // Wave w copies segments g = w + NW q (run g / kChunks, chunk g % kChunks), q = 0..kCopies-1,
-    // lane l's 16 bytes landing at +16 l; runs 0-7 come from the left operand.  (The macro's own
-    // names end in '_' so that arguments cannot capture them.)
+    // lane l's 16 bytes landing at +16 l; runs below kLeftRuns come from the left operand.  (The
+    // macro's own names end in '_' so that arguments cannot capture them.)
 #define MOD_COPY(st, b)                                                                           \
     do {                                                                                          \
         _Pragma("unroll") for (int cq_ = 0; cq_ < kCopies; ++cq_) {                               \
             const int g_ = wave + NW * cq_, r_ = g_ / kChunks, c_ = g_ % kChunks;                 \
-            const int8_t *src_ = (r_ < 8 ? Lg + (long long)r_ * cbytes : Rg + (long long)(r_ - 8) * cbytes) + \
+            const int8_t *src_ = (r_ < kLeftRuns ? Lg + (long long)r_ * cbytes                    \
+                                                 : Rg + (long long)(r_ - kLeftRuns) * cbytes) +   \
                                  ((long long)(st) * kChunks + c_) * 1024 + lane * 16;             \
             __builtin_amdgcn_global_load_lds((const int __attribute__((address_space(1))) *)src_,   \
                 (int __attribute__((address_space(3))) *)(smem + (b) * kStageBytes + r_ * kRunBytes + c_ * 1024), \
@@ -142,23 +148,19 @@ __global__ __launch_bounds__(NW * 64, 1) void hs_mod_i8_kernel(const ModProblemD
         }                                                                                         \
     } while (0)
 
-    // fragments of 32-row group g of a stage: evaluations at j at +2048 g, at -j at +2048 g + 1024;
-    // lane (half, col) holds rows 16 half .. 16 half + 15 of column col
+    // fragments of 32-row group g of a stage: evaluations at j at +2048 g, at -j at +2048 g + 1024
+    // (E = 0, 1); lane (half, col) holds rows 16 half .. 16 half + 15 of column col
     const int half = lane >> 5, col = lane & 31;
     const int la0 = (WM * wm) * kRunBytes + half * 512 + col * 16;
-    const int lb0 = (8 + WN * wn) * kRunBytes + half * 512 + col * 16;
+    const int lb0 = (kLeftRuns + WN * wn) * kRunBytes + half * 512 + col * 16;
     v4i a1[WM], a2[WM], b1[WN], b2[WN];
-#define MOD_READ(slot, grp, A1, A2, B1, B2)                                                       \
+#define MOD_READ(slot, grp, E, A, B)                                                              \
     do {                                                                                          \
-        const unsigned char *st_ = smem + (slot) * kStageBytes + (grp) * 2048;                    \
-        _Pragma("unroll") for (int i_ = 0; i_ < WM; ++i_) {                                       \
-            A1[i_] = *reinterpret_cast<const v4i *>(st_ + la0 + i_ * kRunBytes);                  \
-            A2[i_] = *reinterpret_cast<const v4i *>(st_ + la0 + i_ * kRunBytes + 1024);           \
-        }                                                                                         \
-        _Pragma("unroll") for (int j_ = 0; j_ < WN; ++j_) {                                       \
-            B1[j_] = *reinterpret_cast<const v4i *>(st_ + lb0 + j_ * kRunBytes);                  \
-            B2[j_] = *reinterpret_cast<const v4i *>(st_ + lb0 + j_ * kRunBytes + 1024);           \
-        }                                                                                         \
+        const unsigned char *st_ = smem + (slot) * kStageBytes + (grp) * 2048 + (E) * 1024;       \
+        _Pragma("unroll") for (int i_ = 0; i_ < WM; ++i_)                                         \
+            A[i_] = *reinterpret_cast<const v4i *>(st_ + la0 + i_ * kRunBytes);                   \
+        _Pragma("unroll") for (int j_ = 0; j_ < WN; ++j_)                                         \
+            B[j_] = *reinterpret_cast<const v4i *>(st_ + lb0 + j_ * kRunBytes);                   \
     } while (0)
 
     // all kRing slots filled; wait for stage 0 (later stages may stay in flight), read its first group
@@ -166,7 +168,8 @@ __global__ __launch_bounds__(NW * 64, 1) void hs_mod_i8_kernel(const ModProblemD
     for (int s0 = 0; s0 < kRing; ++s0)
         if (s0 < nst) MOD_COPY(s0, s0);
     ring_wait<kCopies, kRing - 1>(min(kRing - 1, nst - 1));
-    MOD_READ(0, 0, a1, a2, b1, b2);
+    MOD_READ(0, 0, 0, a1, b1);
+    MOD_READ(0, 0, 1, a2, b2);
 
     int b = 0;                                    // ring slot of stage st
     for (int st0 = 0; st0 < nst; st0 += kFlushStages) {
@@ -175,42 +178,30 @@ __global__ __launch_bounds__(NW * 64, 1) void hs_mod_i8_kernel(const ModProblemD
             const int bn = b == kRing - 1 ? 0 : b + 1;      // slot of stage st + 1
 #pragma unroll
             for (int gg = 0; gg < kGroups; ++gg) {
-                v4i na1[WM], na2[WM], nb1[WN], nb2[WN];
-                if (gg + 1 < kGroups) {
-                    MOD_READ(b, gg + 1, na1, na2, nb1, nb2);
-                } else if (st + 1 < nst) {
-                    // stage st + 1 landed for everyone; stage st is no longer read
-                    ring_wait<kCopies, kRing - 1>(min(kRing - 2, nst - st - 2));
-                    MOD_READ(bn, 0, na1, na2, nb1, nb2);
-                }
-                // keep the reads ahead of this group's products (the scheduler would sink them)
-                __builtin_amdgcn_sched_barrier(0);
+                const bool last = gg + 1 == kGroups;
+                const bool more = !last || st + 1 < nst;
+                const int nslot = last ? bn : b, ngrp = last ? 0 : gg + 1;
 #pragma unroll
                 for (int i = 0; i < WM; ++i)
 #pragma unroll
                     for (int j = 0; j < WN; ++j)
                         acc[i][j][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1[i], b1[j], acc[i][j][0], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                // stage st + 1 landed for everyone; stage st is no longer read
+                if (last && st + 1 < nst) ring_wait<kCopies, kRing - 1>(min(kRing - 2, nst - st - 2));
+                if (more) MOD_READ(nslot, ngrp, 0, a1, b1);
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int i = 0; i < WM; ++i)
 #pragma unroll
                     for (int j = 0; j < WN; ++j)
                         acc[i][j][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2[i], b2[j], acc[i][j][1], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (more) MOD_READ(nslot, ngrp, 1, a2, b2);
                 // refill the slot of stage st (free since the barrier) after the products are queued: a
                 // copy issued before them can hold the wave while the memory queue drains
+                if (last && st + kRing < nst) MOD_COPY(st + kRing, b);
                 __builtin_amdgcn_sched_barrier(0);
-                if (gg + 1 == kGroups && st + kRing < nst) MOD_COPY(st + kRing, b);
-                if (gg + 1 < kGroups || st + 1 < nst) {
-#pragma unroll
-                    for (int i = 0; i < WM; ++i) {
-                        a1[i] = na1[i];
-                        a2[i] = na2[i];
-                    }
-#pragma unroll
-                    for (int j = 0; j < WN; ++j) {
-                        b1[j] = nb1[j];
-                        b2[j] = nb2[j];
-                    }
-                }
             }
             b = bn;
         }
@@ -240,14 +231,14 @@ __global__ __launch_bounds__(NW * 64, 1) void hs_mod_i8_kernel(const ModProblemD
             }
 
     // residues of each 32 x 32 tile (block row r, column c), stored per 128 x 128 tile
-    // (2I + r / 4, J) as [64 x 64 quarter (r / 2 % 2, c / 2)][r % 2][c % 2][re, im][lane][16 bytes];
-    // tiles below the diagonal are skipped
+    // ((BR/128) I + r / 4, J) as [64 x 64 quarter (r / 2 % 2, c / 2)][r % 2][c % 2][re, im][lane]
+    // [16 bytes]; tiles below the diagonal are skipped
     const int slot0 = mat * pb.ntri;
     int8_t *out0 = pb.res + (long long)mo * 2 * pb.ntri * kResTileBytes;
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
         const int r = WM * wm + i;
-        const int ti = 2 * td.ti + (r >> 2);
+        const int ti = (BR / 128) * td.ti + (r >> 2);
         if (ti > td.tj) continue;
         int8_t *out = out0 + (long long)(slot0 + tri_index(ti, td.tj)) * kResTileBytes;
 #pragma unroll
@@ -271,19 +262,19 @@ __global__ __launch_bounds__(NW * 64, 1) void hs_mod_i8_kernel(const ModProblemD
     }
 }
 
-template <int CH, int NW>
+template <int CH, int BR>
 hipError_t set_mod_lds()
 {
-    using G = ModStage<CH, NW>;
-    return hipFuncSetAttribute((const void *)hs_mod_i8_kernel<CH, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    using G = ModStage<CH, BR>;
+    return hipFuncSetAttribute((const void *)hs_mod_i8_kernel<CH, BR>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                G::kRing * G::kStageBytes);
 }
 
-template <int CH, int NW>
+template <int CH, int BR>
 void launch_mod_variant(const ModProblemDev *probs, const TileDev *tiles, int n_tiles, const ModTable &mt, hipStream_t s)
 {
-    using G = ModStage<CH, NW>;
-    hipLaunchKernelGGL((hs_mod_i8_kernel<CH, NW>), dim3(n_tiles, mt.nm), dim3(NW * 64), G::kRing * G::kStageBytes, s,
+    using G = ModStage<CH, BR>;
+    hipLaunchKernelGGL((hs_mod_i8_kernel<CH, BR>), dim3(n_tiles, mt.nm), dim3(512), G::kRing * G::kStageBytes, s,
                        probs, tiles, mt);
 }
 
@@ -293,8 +284,8 @@ hipError_t init_mod_kernels()
 {
     static hipError_t done = hipErrorNotReady;
     if (done == hipSuccess) return done;
-    hipError_t e = set_mod_lds<4, 8>();
-    if (e == hipSuccess) e = set_mod_lds<2, 8>();
+    hipError_t e = set_mod_lds<4, 256>();
+    if (e == hipSuccess) e = set_mod_lds<2, 256>();
     done = e;
     return done;
 }
@@ -305,8 +296,8 @@ hipError_t launch_mod_contract(const ModProblemDev *probs, const TileDev *tiles,
 {
     hipError_t e = init_mod_kernels();
     if (e != hipSuccess) return e;
-    if (chunks == 2) launch_mod_variant<2, 8>(probs, tiles, n_tiles, mt, s);
-    else if (chunks == 4) launch_mod_variant<4, 8>(probs, tiles, n_tiles, mt, s);
+    if (chunks == 2) launch_mod_variant<2, 256>(probs, tiles, n_tiles, mt, s);
+    else if (chunks == 4) launch_mod_variant<4, 256>(probs, tiles, n_tiles, mt, s);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
