@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kThreads, 1) void lds_read_kernel(int steps, long l
 }
 
 struct Rate {
-    double tbs, bpc;
+    double tbs, bpc, ghz;
 };
 
 // bytes moved per work-group; rate over the device (event time) and per CU per clock
@@ -116,8 +116,8 @@ Rate measure(void (*launch)(long long *, int *), double bytes_per_block)
 {
     long long *clk;
     int *out;
-    if (hipMalloc(&clk, 4 * kBlocks * sizeof(long long)) != hipSuccess) return {-1, -1};
-    if (hipMalloc(&out, kBlocks * kThreads * sizeof(int)) != hipSuccess) return {-1, -1};
+    if (hipMalloc(&clk, 4 * kBlocks * sizeof(long long)) != hipSuccess) return {-1, -1, -1};
+    if (hipMalloc(&out, kBlocks * kThreads * sizeof(int)) != hipSuccess) return {-1, -1, -1};
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
@@ -130,12 +130,16 @@ Rate measure(void (*launch)(long long *, int *), double bytes_per_block)
     (void)hipEventElapsedTime(&ms, e0, e1);
     long long h[4 * kBlocks];
     (void)hipMemcpy(h, clk, sizeof h, hipMemcpyDeviceToHost);
-    double cyc = 0.0;
-    for (int b = 0; b < kBlocks; ++b) cyc += (double)(h[4 * b + 2] - h[4 * b]);
+    double cyc = 0.0, rt = 0.0;
+    for (int b = 0; b < kBlocks; ++b) {
+        cyc += (double)(h[4 * b + 2] - h[4 * b]);
+        rt += (double)(h[4 * b + 3] - h[4 * b + 1]);
+    }
     cyc /= kBlocks;
+    rt /= kBlocks;
     (void)hipFree(clk);
     (void)hipFree(out);
-    return {bytes_per_block * kBlocks / (ms * 1e-3) / 1e12, bytes_per_block / cyc};
+    return {bytes_per_block * kBlocks / (ms * 1e-3) / 1e12, bytes_per_block / cyc, cyc / (rt / 100e6) / 1e9};
 }
 
 const char *g_src = nullptr;
@@ -181,8 +185,9 @@ int main()
     g_steps = 200000;
     const Rate lds = measure(launch_lds, (double)kWaves * 8 * 1024 * g_steps);
     (void)hipFree(src);
-    std::printf("{\"l2_lds_dma_tbs\": %.2f, \"l2_lds_dma_bpc\": %.1f, \"l2_lds_reg_tbs\": %.2f, \"l2_lds_reg_bpc\": %.1f, "
-                "\"hbm_lds_dma_tbs\": %.2f, \"hbm_lds_dma_bpc\": %.1f, \"lds_read_tbs\": %.2f, \"lds_read_bpc\": %.1f}\n",
-                dma.tbs, dma.bpc, reg.tbs, reg.bpc, hbm.tbs, hbm.bpc, lds.tbs, lds.bpc);
+    std::printf("{\"l2_lds_dma_tbs\": %.2f, \"l2_lds_dma_bpc\": %.1f, \"l2_lds_dma_ghz\": %.2f, \"l2_lds_reg_tbs\": %.2f, "
+                "\"l2_lds_reg_bpc\": %.1f, \"hbm_lds_dma_tbs\": %.2f, \"hbm_lds_dma_bpc\": %.1f, \"lds_read_tbs\": %.2f, "
+                "\"lds_read_bpc\": %.1f, \"lds_read_ghz\": %.2f}\n",
+                dma.tbs, dma.bpc, dma.ghz, reg.tbs, reg.bpc, hbm.tbs, hbm.bpc, lds.tbs, lds.bpc, lds.ghz);
     return 0;
 }
