@@ -2,7 +2,8 @@
 // the integer products are computed modulo several pairwise coprime odd moduli p_m <= 255 on the int8
 // matrix cores, then rebuilt by the Chinese remainder theorem in FP64.  (The paper computes these
 // updates in FP64 BLAS, sections 4.2-4.6; this is an alternative to the digit scheme of split.hip
-// that needs one int8 product per modulus instead of one per kept digit pair.)
+// whose work grows with the number of moduli, each worth about 7.5 bits, instead of with the number
+// of kept digit pairs, and whose complex products take half the matrix-core work of a digit pair's.)
 //
 // Integers.  Operand column c (a basis function) is scaled by s_c = 2^B / ||X_c|| (the 2-norm of the
 // column over all contraction rows, real and imaginary parts; s_c rounded down to 8 significant
