@@ -10,12 +10,12 @@
 // int32 accumulator; accumulators are reduced mod p every kFlushStages stages (65536 rows), so they
 // stay below 2^31.  The epilogue turns z1, z2 into Re = (z1 + z2) / 2 and Im = (z1 - z2) / (2 j).
 //
-//   hs_mod_i8_kernel<CH, NW> one block per (256 x 128 output block, modulus): NW = 8 waves of
-//                       64 x 64, stages of 16 CH rows copied to LDS by global_load_lds into a ring
-//                       of three (CH = 4) or four (CH = 2) buffers, the younger stages in flight;
-//                       the fragments of the next 32-row group read while the current group's
-//                       MFMAs run, across stage boundaries too; writes the residues of Re and Im
-//                       (int8, 32 KB per 128 x 128 tile) to the problem's scratch
+//   hs_mod_i8_kernel<CH, BR> one block per (BR x 128 output block, modulus), BR = 256: eight
+//                       waves of 64 x 64, stages of 16 CH rows copied to LDS by global_load_lds into
+//                       a ring of three (CH = 4) or four (CH = 2) buffers, the younger stages in
+//                       flight; each half of a group's products (first, second evaluation) issued
+//                       while the other half's next fragments are read; writes the residues of Re
+//                       and Im (int8, 32 KB per 128 x 128 tile) to the problem's scratch
 #include "context.hpp"
 
 namespace flapw {
@@ -26,7 +26,8 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 // Stage geometry for CH 16-row chunks per LDS stage (CH = 4: 64-row stages; CH = 2: 32-row
-// stages) and blocks of BR x 128 (BR = 256 or 384 rows; eight waves of BR/4 x 64).  A stage is
+// stages) and blocks of BR x 128 (eight waves of BR/4 x 64).  The library launches BR = 256; 384
+// also compiles but needs more accumulator registers than two waves per SIMD hold.  A stage is
 // BR/32 left and 4 right 32-column runs of CH 1 KB segments.
 template <int CH, int BR>
 struct ModStage {
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(512, 1) void hs_mod_i8_kernel(const ModProblemDev *
 #undef MOD_READ
 #undef MOD_COPY
     // Re = (z1 + z2) / 2, Im = (z1 - z2) / (2 j) mod p (|z1 +- z2| <= 6p after the flush step,
-    // inverses in the symmetric range: the products stay below 2^17)
+    // inverses in the symmetric range: the products stay below 2^18, exact in float)
     const int h2 = mt.h2[mo], h2j = mt.h2j[mo];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
