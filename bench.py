@@ -227,6 +227,16 @@ def copy_ceiling():
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def contraction_rows(lmax_atoms, lnonsph: int) -> int:
+    """Rows of A (or of B) the H contraction covers when S comes from the addition theorem: with a
+    structured T (lnonsph >= 0) only the (min(l_max, lnonsph) + 1)^2 rows of each atom, the
+    L-diagonal rest being added by the Legendre kernel; all K rows otherwise."""
+    lm = np.asarray(lmax_atoms, dtype=np.int64)
+    if lnonsph >= 0:
+        lm = np.minimum(lm, lnonsph)
+    return int(((lm + 1) ** 2).sum())
+
+
 def mod_copy_bytes(n: int, kp2: int, nm: int) -> int:
     """Bytes the modular contraction copies from L2 into LDS for one k-point: every 256 x 128 block
     of the S and the H upper triangles (2I <= J over 128-column tiles, N padded to 256 columns), per
@@ -455,8 +465,11 @@ def main():
     f_alg = [cell.flops_per_k(i) for i in range(nk)]
     kr = cell.k_rows()
     # algorithmic flops of the contraction kernel: S and H triangles, or H alone when S comes from
-    # the addition theorem
+    # the addition theorem, over the rows it contracts (with S by the addition theorem and a
+    # structured T, only the rows of l <= l_nonsph)
     per_mat = [8.0 * kr * cell.n_g(i) * (cell.n_g(i) + 1.0) for i in range(nk)]
+    k_cut = contraction_rows(cell.lmax[cell.atom_type], args.lnonsph)
+    per_mat_cut = [8.0 * k_cut * cell.n_g(i) * (cell.n_g(i) + 1.0) for i in range(nk)]
     idx = sample_indices(cell.n_g(0), args.cpu_sample)
 
     def split_path(path):
@@ -472,7 +485,7 @@ def main():
     for pi, path in enumerate(precs):
         is_head = pi == 0
         prec, s_method = split_path(path)
-        f_contract = [(2.0 if s_method == "gemm" else 1.0) * x for x in per_mat]
+        f_contract = [2.0 * x for x in per_mat] if s_method == "gemm" else per_mat_cut
         n_warm, n_time, n_eager = step_plan(is_head, args.steps, args.warmup)
         use_graph = not (is_head and args.eager)
         notes = []
@@ -599,10 +612,11 @@ def main():
             "unit": "TFLOP/s" if head == "fp64" else "TOP/s",
             "frac": (achieved / PEAKS[head]) if achieved else None, "traffic": traffic,
             "avg_launch_ms": k_ms, "launches_per_step": n_launch,
-            "flops_per_launch": sum(per_mat) * (2.0 if head_method == "gemm" else 1.0) / n_launch,
+            "flops_per_launch": (2.0 * sum(per_mat) if head_method == "gemm" else sum(per_mat_cut)) / n_launch,
             "algorithmic_unit": ("FP64-equivalent flops of the S and H upper triangles (8 K N(N+1) each)"
                                  if head_method == "gemm" else
-                                 "FP64-equivalent flops of the H upper triangle (8 K N(N+1)); S by the addition theorem")}
+                                 "FP64-equivalent flops of the H upper triangle (8 K' N(N+1), K' the rows the "
+                                 "structured T contracts, K without one); S by the addition theorem")}
     if head != "fp64" and achieved:
         # the split path's FP64-equivalent rate against the FP64 matrix-core roofline it replaces
         roof["fp64_roofline_frac"] = achieved / PEAKS["fp64"]

@@ -108,3 +108,10 @@ def test_mod_copy_bytes_counts_the_blocks_of_both_triangles():
     each copying 24 KB per 32-row group for every modulus."""
     assert bench.mod_copy_bytes(11621, 123904, 11) == 2 * 11 * 2162 * (123904 // 32) * 24576
     assert bench.mod_copy_bytes(256, 256, 8) == 2 * 8 * 2 * 8 * 24576
+
+
+def test_contraction_rows_of_a_structured_t():
+    """With S by the addition theorem and l_nonsph = 6, an l_max 10 atom contributes 49 rows of A
+    instead of 121; an l_max 4 atom keeps its 25; without a structured T all rows count."""
+    assert bench.contraction_rows([10, 10, 4], 6) == 49 + 49 + 25
+    assert bench.contraction_rows([10, 10, 4], -1) == 121 + 121 + 25
