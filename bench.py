@@ -609,7 +609,9 @@ def main():
     slices = args.slices or ((r["tuned"] or {}).get("slices") or DEFAULT_SLICES.get(head, 0))
     traffic = read_traffic(head, cell.name, slices) if head_method == "gemm" else None
     roof = {"bound": "mfma", "kernel": KERNEL[head], "achieved": achieved, "peak": PEAKS[head],
-            "unit": "TFLOP/s" if head == "fp64" else "TOP/s",
+            # achieved counts algorithmic FP64-equivalent flops; peak is the path's own matrix-core
+            # peak (int8 operations for the split paths, 5.0 POP/s = 5000 T per second)
+            "unit": "TFLOP/s", "peak_unit": "TFLOP/s" if head == "fp64" else "TOP/s (int8 operations)",
             "frac": (achieved / PEAKS[head]) if achieved else None, "traffic": traffic,
             "avg_launch_ms": k_ms, "launches_per_step": n_launch,
             "flops_per_launch": (2.0 * sum(per_mat) if head_method == "gemm" else sum(per_mat_cut)) / n_launch,
