@@ -19,6 +19,7 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libflapw_hip.so")
 MFMA_RATE = os.path.join(HERE, "mfma_rate")                  # matrix-core ceiling microbenchmark
 COPY_RATE = os.path.join(HERE, "copy_rate")                  # L2 -> LDS copy and LDS read rates
+MOD_BLOCKS = os.path.join(HERE, "mod_blocks")                # block shapes of the modular contraction
 ARCH = "gfx950"
 
 
@@ -76,8 +77,13 @@ def build(verbose: bool = False) -> str:
                        text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for copy_rate.hip:\n" + r.stdout + r.stderr)
+    src = os.path.join(HERE, "microbench", "mod_blocks.hip")
+    r = subprocess.run([_hipcc()] + [f for f in FLAGS if f != "-fPIC"] + [src, "-o", MOD_BLOCKS], capture_output=True,
+                       text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for mod_blocks.hip:\n" + r.stdout + r.stderr)
     if verbose:
-        print("built", LIB, MFMA_RATE, "and", COPY_RATE)
+        print("built", LIB, MFMA_RATE, COPY_RATE, "and", MOD_BLOCKS)
     return LIB
 
 
