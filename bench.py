@@ -239,10 +239,11 @@ def contraction_rows(lmax_atoms, lnonsph: int) -> int:
 
 def mod_copy_bytes(n: int, kp2: int, nm: int) -> int:
     """Bytes the modular contraction copies from L2 into LDS for one k-point: every 256 x 128 block
-    of the S and the H upper triangles (2I <= J over 128-column tiles, N padded to 256 columns), per
-    modulus, copies 24 KB per 32-row group (256 + 128 columns x 2 evaluations x 32 bytes)."""
-    nt = 2 * ((n + 255) // 256)
-    blocks = sum(nt - 2 * i for i in range(nt // 2))
+    of the S and the H upper triangles (2I <= J over the ceil(N / 128) column tiles that hold
+    columns), per modulus, copies 24 KB per 32-row group (256 + 128 columns x 2 evaluations x 32
+    bytes)."""
+    nt = (n + 127) // 128
+    blocks = sum(nt - 2 * i for i in range((nt + 1) // 2))
     return 2 * nm * blocks * (kp2 // 32) * 24576
 
 

@@ -394,13 +394,15 @@ void build_tiles(const std::vector<int> &np_tiles, int m0, int m1, std::vector<T
 }
 
 // Blocks of the modular contraction: rows 256 I .. 256 I + 255 (128-row tiles 2I, 2I + 1) by
-// columns 128 J .. 128 J + 127, for the upper triangle (2I <= J); np_tiles counts 128-column
-// tiles and is even.  Bands of kBand block rows walk the columns, as in build_tiles.
-void build_mod_tiles(const std::vector<int> &np_tiles, int m0, int m1, std::vector<TileDev> &out, int kBand)
+// columns 128 J .. 128 J + 127, for the upper triangle (2I <= J); nc_tiles counts the 128-column
+// tiles that hold columns, ceil(n / 128), so that a tile of padding columns only (the residue
+// planes are 256-column aligned) costs no block.  Bands of kBand block rows walk the columns, as in
+// build_tiles.
+void build_mod_tiles(const std::vector<int> &nc_tiles, int m0, int m1, std::vector<TileDev> &out, int kBand)
 {
     std::vector<TileDev> order;
-    for (int p = 0; p < (int)np_tiles.size(); ++p) {
-        const int nt = np_tiles[p], nb = nt / 2;
+    for (int p = 0; p < (int)nc_tiles.size(); ++p) {
+        const int nt = nc_tiles[p], nb = (nt + 1) / 2;
         for (int b0 = 0; b0 < nb; b0 += kBand)
             for (int tj = 2 * b0; tj < nt; ++tj)
                 for (int bi = b0; bi < std::min(b0 + kBand, tj / 2 + 1); ++bi)
@@ -864,7 +866,7 @@ flapw_status prepare_generate(flapw_handle h, int n_k, const double *k, const in
         for (int i = bt.i0; i < bt.i1; ++i) {
             if (p.mod) {
                 const ModArea ma = mod_area(p.digits + p.off[i], L.kp2, p.np[i], p.sl);
-                npt.push_back((int)(ma.npm / kModTile));
+                npt.push_back((int)((n_g[i] + kModTile - 1) / kModTile));   // tiles holding columns
                 mprobs.push_back(mod_problem(ma, (double2 *)H[i], (double2 *)S[i], (long long)ldh[i], n_g[i], L.kp2));
                 continue;
             }
@@ -1266,8 +1268,8 @@ flapw_status hs_contract_impl(flapw_handle h, int n_g, const flapw_atoms *at, co
     if (mod) {
         area = (size_t)mod_area_bytes(L.kp2, np, sl);
         npm = round_up(np, 2 * kModTile);
-        build_mod_tiles({(int)(npm / kModTile)}, 0, 2, blocks, band);
-        build_tiles({(int)(npm / kModTile)}, 0, 2, tiles, band);
+        build_mod_tiles({(int)((n_g + kModTile - 1) / kModTile)}, 0, 2, blocks, band);
+        build_tiles({(int)((n_g + kModTile - 1) / kModTile)}, 0, 2, tiles, band);
     } else if (split) {
         area = (size_t)digit_area_bytes(L.kp2, np, sl, digit_bytes(prec));
         build_tiles({(int)(np / kTile)}, 0, 2, tiles, band);

@@ -135,6 +135,16 @@ __global__ __launch_bounds__(256) void mod_colsum_kernel(const double *__restric
     sRH[c] = mod_scale(sq, two2b);
 }
 
+// The low bytes of four int32 values packed into one word (byte k from value k) by two byte
+// permutes (v_perm_b32: selector values 0-3 take the bytes of the second source, 4-7 those of the
+// first, 0x0c a zero byte) and an or, where masking and shifting each byte takes two instructions.
+__device__ inline unsigned pack_low_bytes(int b0, int b1, int b2, int b3)
+{
+    const unsigned lo = __builtin_amdgcn_perm((unsigned)b1, (unsigned)b0, 0x0c0c0400u);
+    const unsigned hi = __builtin_amdgcn_perm((unsigned)b3, (unsigned)b2, 0x04000c0cu);
+    return lo | hi;
+}
+
 // Residues of 16 Gaussian integers xr + i xi (integer-valued doubles, |xr|, |xi| <= 2^50 (1 + 2^-15))
 // for every modulus, as the evaluations xr + sg j xi (16 bytes at out0 + m mstride) and xr - sg j xi
 // (at out1 + m mstride); sg = -1 stores the conjugate.  xi is reduced first (c = xi mod p, exact in
@@ -148,17 +158,17 @@ __device__ inline void write_residues(const double (&xr)[16], const double (&xi)
         unsigned w0[4], w1[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            unsigned u0 = 0, u1 = 0;
+            int v0[4], v1[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const double x = xi[4 * q + b];
                 const double c = fma(-rint(x * ip), p, x);             // xi mod p, exact
                 const double r = xr[4 * q + b];
-                u0 |= ((unsigned)sym_mod(fma(js, c, r), p, ip) & 0xffu) << (8 * b);
-                u1 |= ((unsigned)sym_mod(fma(-js, c, r), p, ip) & 0xffu) << (8 * b);
+                v0[b] = sym_mod(fma(js, c, r), p, ip);
+                v1[b] = sym_mod(fma(-js, c, r), p, ip);
             }
-            w0[q] = u0;
-            w1[q] = u1;
+            w0[q] = pack_low_bytes(v0[0], v0[1], v0[2], v0[3]);
+            w1[q] = pack_low_bytes(v1[0], v1[1], v1[2], v1[3]);
         }
         *reinterpret_cast<uint4 *>(out0 + m * mstride) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
         *reinterpret_cast<uint4 *>(out1 + m * mstride) = make_uint4(w1[0], w1[1], w1[2], w1[3]);

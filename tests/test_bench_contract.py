@@ -104,10 +104,12 @@ def test_error_estimate_reweights_the_sample():
 
 
 def test_mod_copy_bytes_counts_the_blocks_of_both_triangles():
-    """N = 11621 pads to 92 tiles of 128 columns: 2162 blocks of 256 x 128 with 2I <= J per matrix,
-    each copying 24 KB per 32-row group for every modulus."""
-    assert bench.mod_copy_bytes(11621, 123904, 11) == 2 * 11 * 2162 * (123904 // 32) * 24576
+    """N = 11621 spans 91 tiles of 128 columns (the 92nd, padding only, gets no block): 2116 blocks
+    of 256 x 128 with 2I <= J per matrix, each copying 24 KB per 32-row group for every modulus."""
+    assert bench.mod_copy_bytes(11621, 123904, 11) == 2 * 11 * 2116 * (123904 // 32) * 24576
+    assert bench.mod_copy_bytes(11520, 128, 11) == 2 * 11 * 2070 * 4 * 24576      # 90 tiles, no padding tile
     assert bench.mod_copy_bytes(256, 256, 8) == 2 * 8 * 2 * 8 * 24576
+    assert bench.mod_copy_bytes(129, 32, 8) == 2 * 8 * 2 * 1 * 24576
 
 
 def test_contraction_rows_of_a_structured_t():
