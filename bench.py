@@ -626,6 +626,12 @@ def main():
         ex = achieved * executed_per_flop(slices, head)
         roof.update({"executed_ops_per_flop": executed_per_flop(slices, head), "executed_achieved": ex,
                      "executed_frac": ex / PEAKS[head], "slices": slices})
+        if head == "i8mod":
+            roof["bound_evidence"] = (
+                "board power: on streamed random residues the int8 matrix cores issue at about 0.87 G "
+                "busy cycles per second per SIMD (about 1.8 POP/s executed) for 256 x 128 and 256 x 256 "
+                "blocks alike; with zero residues the same kernel runs at the full clock "
+                "(profiles/power_bound_hs_mod_c4_scale.md)")
     ceil = mfma_ceiling() if args.ceiling else None
     copies = copy_ceiling() if args.ceiling and head == "i8mod" else None
     if copies:
